@@ -1,0 +1,53 @@
+"""Seeded synthetic inputs shared by the oracle pins and the GPU parity tests.
+
+This module holds no arithmetic of the method: only problem set-ups (mesh
+sizes, boundary kinds, Eq. 63 parameters derived by the caller), analytic
+initial fields and seeded random numbers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PERIODIC, WALL_ISOTHERMAL, WALL_ADIABATIC = 0, 1, 2
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def dhc_bc(dim: int = 2, hot_low: bool = True):
+    """Differentially heated cavity: isothermal walls on x (hot at x = 0 when
+    hot_low), adiabatic elsewhere, gravity along +y (2D) / +z (3D) upward."""
+    hot, cold = (0.5, -0.5) if hot_low else (-0.5, 0.5)
+    if dim == 2:
+        bc = (WALL_ISOTHERMAL, WALL_ISOTHERMAL, WALL_ADIABATIC, WALL_ADIABATIC, PERIODIC, PERIODIC)
+        return bc, (hot, cold, 0.0, 0.0, 0.0, 0.0), 1
+    bc = (WALL_ISOTHERMAL, WALL_ISOTHERMAL, WALL_ADIABATIC, WALL_ADIABATIC, WALL_ADIABATIC, WALL_ADIABATIC)
+    return bc, (hot, cold, 0.0, 0.0, 0.0, 0.0), 2
+
+
+def rb_bc():
+    """Rayleigh-Benard box: periodic in x, hot bottom / cold top, gravity +y."""
+    bc = (PERIODIC, PERIODIC, WALL_ISOTHERMAL, WALL_ISOTHERMAL, PERIODIC, PERIODIC)
+    return bc, (0.0, 0.0, 0.5, -0.5, 0.0, 0.0), 1
+
+
+def gaussian_hill(xc: np.ndarray, yc: np.ndarray, L: float, t: float, chi: float, u0: float) -> np.ndarray:
+    """Eq. 67 on the periodic box [0, 2L]^2 with x0 = (0.5 L, 0), sigma = 0.05 L,
+    T0 = 2 pi sigma^2 (so the initial peak is 1); minimum-image distances."""
+    sig = 0.05 * L
+    s2 = 2.0 * chi * t + sig * sig
+    X, Y = np.meshgrid(xc, yc)
+    dx = (X - 0.5 * L - u0 * t + L) % (2.0 * L) - L
+    dy = (Y + L) % (2.0 * L) - L
+    return sig * sig / s2 * np.exp(-(dx * dx + dy * dy) / (2.0 * s2))
+
+
+def random_state(N: int, dim: int, seed: int, amp_rho=1e-3, amp_u=0.02, amp_T=0.2):
+    """Seeded smooth-ish random absolute primitives (rho, u[dim, N], T) used for
+    short-horizon parity runs."""
+    g = rng(seed)
+    rho = 1.0 + amp_rho * g.uniform(-1, 1, N)
+    u = amp_u * g.uniform(-1, 1, (dim, N))
+    T = 0.5 + amp_T * g.uniform(-1, 1, N)
+    return rho, u, T
