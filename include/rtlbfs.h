@@ -1,0 +1,231 @@
+/*
+ * rtlbfs.h -- C ABI of the MI355X (gfx950) RTLBFS time-step library.
+ *
+ * The library advances the reconstructed thermal lattice Boltzmann flux solver
+ * (RTLBFS) of Lu, Dai & Yu, arXiv 2202.13449, on structured uniform or
+ * tanh-stretched (Eq. 74) meshes in 2D and 3D:
+ *   predictor  Sec. 3.2(a): at every interior face a face-centred unit lattice
+ *              (D2Q9 / D3Q19 offsets, Fig. 2) is filled by the one-sided linear
+ *              reconstruction of Eq. 29 from Eq. 55 cell gradients (face values
+ *              by Eq. 56); Eqs. 46-48 are evaluated by central differences on
+ *              the lattice to give rho*, (rho u)*, (rho c_p T)*;
+ *   corrector  Sec. 3.2(b): face fluxes of Eqs. 57-59 with the viscous and
+ *              (tau - 1.5) dissipation terms, forward-Euler update (Eqs. 41-43)
+ *              with the Boussinesq force of Eq. 64 (applied in the update and in
+ *              the predicted momentum);
+ *   diagnostics  Eq. 65 residual, Eq. 69 volume Nusselt number, wall Nusselt
+ *              numbers (Eqs. 75-76 form), all reduced in FP64 on the GPU.
+ *
+ * Units: lattice units with the finest cell of size 1 and c = 1 (c_s^2 = 1/3),
+ * c_p = 1, rho0 = 1, absolute temperatures T_low = 0 and T_high = 1 so the
+ * reference temperature is T0 = 0.5.  Wall temperatures are given as
+ * deviations T - T0.  Ra, Pr and Ma define nu, chi and beta*g through Eq. 63
+ * with V_c = Ma (in units of c) and L the domain length along the axis of the
+ * two isothermal walls (else along gravity, else along x).
+ *
+ * Conventions for every entry point:
+ *   - returns RTLBFS_OK (0) or a negative RTLBFS_E* code; never aborts, never
+ *     throws across the ABI, never prints;
+ *   - pointers named host_* are host memory owned by the caller; the
+ *     workspace and stream passed to rtlbfs_create belong to the caller and
+ *     must outlive the handle;
+ *   - a handle is used by one host thread at a time; work is enqueued on the
+ *     handle's stream; calls documented as synchronising wait for it;
+ *   - cells are stored x-fastest: index = i + nx*(j + ny*k).
+ */
+#ifndef RTLBFS_H
+#define RTLBFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes -- */
+#define RTLBFS_OK 0
+#define RTLBFS_EINVAL (-1)       /* bad argument or inconsistent problem */
+#define RTLBFS_ENOMEM (-2)       /* device allocation failed or workspace too small */
+#define RTLBFS_EDEVICE (-3)      /* a HIP call failed (text in rtlbfs_last_error) */
+#define RTLBFS_EDIVERGED (-4)    /* NaN/Inf or local Mach > 0.5 seen at a residual step */
+#define RTLBFS_EUNSUPPORTED (-5) /* valid request this build does not implement */
+#define RTLBFS_ESTATE (-6)       /* call order (e.g. a residual before any residual step) */
+
+/* Boundary kinds per side (x-, x+, y-, y+, z-, z+). */
+#define RTLBFS_PERIODIC 0
+#define RTLBFS_WALL_ISOTHERMAL 1 /* no-slip, temperature T0 + Tdev[side] */
+#define RTLBFS_WALL_ADIABATIC 2  /* no-slip, zero heat flux */
+
+/* Storage / arithmetic of the state. */
+#define RTLBFS_FP64_PLAIN 0 /* rho, rho u, rho c_p T in double */
+#define RTLBFS_FP32_DEV 1   /* r = rho - 1, rho u, theta = rho c_p (T - T0) in float */
+#define RTLBFS_FP64_DEV 2   /* the deviation storage in double */
+
+/* Initial state. */
+#define RTLBFS_INIT_REST 0       /* rho = 1, u = 0, T' = 0 (+ noise) */
+#define RTLBFS_INIT_CONDUCTION 1 /* linear T' between the isothermal walls (+ noise) */
+
+/* Field selectors for rtlbfs_get_field: absolute primitives. */
+#define RTLBFS_FIELD_RHO 0
+#define RTLBFS_FIELD_UX 1
+#define RTLBFS_FIELD_UY 2
+#define RTLBFS_FIELD_UZ 3 /* 3D only; in 2D index 3 is T */
+/* The temperature is field dim + 1. */
+
+typedef struct {
+    int dim;           /* 2 or 3 */
+    int n[3];          /* cells per axis; n[2] ignored in 2D; each >= 4 */
+    double stretch[3]; /* 0: unit cells; > 0: Eq. 74 tanh clustering with phi = stretch,
+                          scaled so the smallest cell is 1 (uniform only on periodic axes) */
+} rtlbfs_mesh;
+
+typedef struct {
+    int kind[6];      /* RTLBFS_PERIODIC / _WALL_ISOTHERMAL / _WALL_ADIABATIC per side;
+                         periodic sides come in pairs */
+    double Tdev[6];   /* isothermal wall temperature minus T0 */
+    int gravity_axis; /* buoyancy acts along +axis (the "up" unit vector); -1 none */
+} rtlbfs_bc;
+
+typedef struct {
+    int precision;        /* RTLBFS_FP64_PLAIN (default), _FP32_DEV, _FP64_DEV */
+    double dtl;           /* lattice streaming step delta-t; 0 -> 1 (finest cell) */
+    double dt;            /* time step Delta-t; 0 -> min(0.5, 0.15 / max(nu, chi)) */
+    uint64_t seed;        /* SplitMix64 seed of the initial temperature noise */
+    double noise_amp;     /* T' += noise_amp * U(-1,1), U from SplitMix64(seed, cell) */
+    int init;             /* RTLBFS_INIT_REST or _CONDUCTION */
+    int residual_every;   /* chunk length R: the Eq. 65 residual is evaluated on the last step of
+                             every R-step chunk and of every rtlbfs_step call (0 -> 100) */
+    int mass_fix_every;   /* FP32_DEV: remove the total-mass drift every K steps (0 -> 1000,
+                             < 0 -> never) */
+    int graph_steps;      /* >= 0: every full R-step chunk is replayed from a captured HIP graph;
+                             < 0: kernels are launched one by one */
+    int buoyancy_update_only; /* 1: force only in the cell update (not in m*) */
+    int phys_given;       /* 1: use nu, chi, beta_g below and ignore Ra, Pr, Ma */
+    double nu, chi, beta_g;
+    int tile;             /* kernel tile selector; 0 -> automatic */
+} rtlbfs_opts;
+
+typedef struct {
+    double hot_avg, hot_max;   /* area-weighted mean and maximum over the hot wall */
+    double cold_avg, cold_max; /* same over the cold wall */
+    double volume;             /* Eq. 69 along the heat axis: L/(chi dT) <u_a T - chi d_a T> */
+} rtlbfs_nu;
+
+typedef struct {
+    int64_t cells;
+    int64_t steps;              /* steps advanced so far */
+    double L;                   /* characteristic length used in Eq. 63 */
+    double nu, chi, beta_g;     /* derived or given physics */
+    double tau_f, tau_g;        /* Eqs. 9-10 with dtl */
+    double dtl, dt;
+    double length[3];           /* domain length per axis */
+    int precision;
+    int tile_x, tile_y, tile_z; /* tile the step kernel runs with */
+} rtlbfs_info;
+
+typedef struct rtlbfs_handle *rtlbfs_t;
+typedef struct rtlbfs_batch_handle *rtlbfs_batch_t;
+
+/* Static text for a status code (never NULL). */
+const char *rtlbfs_strerror(int code);
+
+/* Per-handle detail of the last failing call (never NULL; "" when none).
+ * With h == NULL: detail of the last failed rtlbfs_create on this thread. */
+const char *rtlbfs_last_error(rtlbfs_t h);
+
+/* Fill *opts with the defaults described above.  EINVAL on NULL. */
+int rtlbfs_opts_init(rtlbfs_opts *opts);
+
+/* Node coordinates of one mesh axis (Eq. 74 or unit spacing), n+1 values into
+ * host_x; returns the length in *L.  Host only.  EINVAL on n < 1 or NULL. */
+int rtlbfs_mesh_nodes(int n, double stretch, double *host_x, double *L);
+
+/* Device workspace needed for this mesh and precision (bytes, 256-aligned);
+ * 0 when the arguments are invalid. */
+size_t rtlbfs_workspace_bytes(const rtlbfs_mesh *mesh, const rtlbfs_opts *opts);
+
+/* Create a solver for one domain.
+ *   mesh, bc: problem geometry and boundaries (see the structs);
+ *   Ra, Pr, Ma: Eq. 63 inputs (ignored when opts->phys_given);
+ *   opts: NULL for defaults;
+ *   hip_stream: the hipStream_t to enqueue on (NULL = the null stream);
+ *   workspace, ws_bytes: caller-owned device memory of at least
+ *     rtlbfs_workspace_bytes(); NULL makes the library allocate (and free) it;
+ *   out: receives the handle.
+ * Uploads the seeded initial state (synchronising).  Errors: EINVAL
+ * (validation: Ra, Pr > 0, 0 < Ma <= 0.3, n >= 4, paired periodic sides,
+ * uniform mesh on periodic axes, gravity_axis < dim), ENOMEM, EDEVICE. */
+int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, const rtlbfs_bc *bc,
+                  const rtlbfs_opts *opts, void *hip_stream, void *workspace, size_t ws_bytes,
+                  rtlbfs_t *out);
+
+/* Enqueue n >= 0 time steps on the handle's stream and return.  The Eq. 65
+ * residual is evaluated on every residual_every-th step and on the last step
+ * of the call.  Divergence found there is reported by the next synchronising
+ * call as EDIVERGED. */
+int rtlbfs_step(rtlbfs_t h, int64_t n);
+
+/* Wait for the handle's stream.  EDIVERGED if a residual step saw NaN/Inf or
+ * Mach > 0.5. */
+int rtlbfs_sync(rtlbfs_t h);
+
+/* Eq. 65 ratios from the most recent residual step (synchronising):
+ * sum| |u|^{n+1} - |u|^n | / sum |u|^{n+1} and sum|T^{n+1} - T^n| / sum T^{n+1}
+ * with the absolute temperature.  ESTATE before any step. */
+int rtlbfs_residual(rtlbfs_t h, double *res_u, double *res_T);
+
+/* Wall and volume Nusselt numbers of the current state (synchronising).
+ * EINVAL if the problem has no pair of isothermal walls on one axis. */
+int rtlbfs_nusselt(rtlbfs_t h, rtlbfs_nu *out);
+
+/* FP64 integrals of the current state (synchronising):
+ * out[0] = sum (rho - 1) dV, out[1] = sum rho c_p (T - T0) dV, out[2] = volume. */
+int rtlbfs_integrals(rtlbfs_t h, double out[3]);
+
+/* Copy one absolute primitive field (0 rho, 1..dim u_a, dim+1 T) of all
+ * cells into host_out (count >= cells; synchronising). */
+int rtlbfs_get_field(rtlbfs_t h, int field, double *host_out, size_t count);
+
+/* Replace the state by absolute primitives: host_rho[cells], host_u[dim*cells]
+ * (axis-major), host_T[cells]; converted to the handle's storage (synchronising). */
+int rtlbfs_set_state(rtlbfs_t h, const double *host_rho, const double *host_u, const double *host_T,
+                     size_t cells);
+
+/* Stored conserved field f (0..dim+1) converted to double, in the storage
+ * form of the handle (for checkpoints and parity checks; synchronising). */
+int rtlbfs_get_stored(rtlbfs_t h, int field, double *host_out, size_t count);
+
+/* Handle facts (host only, no synchronisation). */
+int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out);
+
+/* Destroy; frees only what the library allocated.  NULL is a no-op. */
+int rtlbfs_destroy(rtlbfs_t h);
+
+/* ----------------------------------------------------------- batched -- */
+/* Many independent 2D domains advanced together: one kernel launch per step
+ * covers the tiles of every member, replayed from a captured HIP graph.
+ * meshes, Ra, Pr and bcs are arrays of `count`; each member has its own
+ * lattice units, Eq. 63 parameters and Delta-t (the dtl/dt defaults apply per
+ * member).  Precision must be the same for all (opts->precision). */
+size_t rtlbfs_batch_workspace_bytes(int count, const rtlbfs_mesh *meshes, const rtlbfs_opts *opts);
+
+int rtlbfs_batch_create(int count, const rtlbfs_mesh *meshes, const double *Ra, const double *Pr, double Ma,
+                        const rtlbfs_bc *bcs, const rtlbfs_opts *opts, void *hip_stream, void *workspace,
+                        size_t ws_bytes, rtlbfs_batch_t *out);
+
+/* Enqueue n steps of every member (each member takes its own Delta-t). */
+int rtlbfs_batch_step(rtlbfs_batch_t h, int64_t n);
+
+/* Per-member diagnostics and fields (synchronising). */
+int rtlbfs_batch_nusselt(rtlbfs_batch_t h, int member, rtlbfs_nu *out);
+int rtlbfs_batch_residual(rtlbfs_batch_t h, int member, double *res_u, double *res_T);
+int rtlbfs_batch_get_field(rtlbfs_batch_t h, int member, int field, double *host_out, size_t count);
+int rtlbfs_batch_get_info(rtlbfs_batch_t h, int member, rtlbfs_info *out);
+int rtlbfs_batch_sync(rtlbfs_batch_t h);
+int rtlbfs_batch_destroy(rtlbfs_batch_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,58 @@
+"""Build the gfx950 HIP library librtlbfs.so in-tree with hipcc.
+
+All device code is compiled for gfx950 only, with packed FP32 instructions
+disabled (they are not used by hand and the compiler is told not to form
+them).
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "librtlbfs.so")
+SOURCES = [os.path.join(CSRC, "rtlbfs_api.hip"), os.path.join(CSRC, "rtlbfs_batch.hip")]
+HEADERS = ["rtlbfs_device.h", "step2d.h", "step3d.h", "reduce.h"]
+
+
+def hipcc() -> str:
+    for c in ("/opt/rocm/bin/hipcc", "hipcc"):
+        if os.path.exists(c) or c == "hipcc":
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose: bool = False, jobs: int = 2) -> str:
+    flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+        cmd = [hipcc()] + flags + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+        if len(procs) >= jobs:
+            p, c = procs.pop(0)
+            if p.wait() != 0:
+                raise RuntimeError("compile failed: " + " ".join(c))
+    for p, c in procs:
+        if p.wait() != 0:
+            raise RuntimeError("compile failed: " + " ".join(c))
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,725 @@
+// rtlbfs_api.hip -- host runtime behind include/rtlbfs.h: validation, mesh
+// (Eq. 74), Eq. 63 parameters, seeded initial state, workspace layout,
+// graph-captured step chunks, FP64 diagnostics and field access.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rtlbfs.h"
+#include "reduce.h"
+#include "rtlbfs_device.h"
+#include "step2d.h"
+#include "step3d.h"
+
+using namespace rtlbfs;
+
+// ----------------------------------------------------------------- kernels --
+
+template <typename R, bool DEV, int TX, int TY, bool RES>
+__global__ void __launch_bounds__(256) k_step2d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
+                                                double *__restrict__ parts) {
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    tile_step_2d<R, DEV, TX, TY, RES>(d, i0, j0, Uin, Uout,
+                                      parts + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * kPartials);
+}
+
+template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
+__global__ void __launch_bounds__(TX * TY * TZ) k_step3d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
+                                                double *__restrict__ parts) {
+    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    tile_step_3d<R, DEV, TX, TY, TZ, RES>(
+        d, bx * TX, by * TY, bz * TZ, Uin, Uout,
+        parts + ((int64_t)(bz * gridDim.y + by) * gridDim.x + bx) * kPartials);
+}
+
+namespace {
+
+constexpr int kTX2 = 32, kTY2 = 8;             // 2D tile
+constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per cell)
+constexpr int kRedBlocks = 512;                // blocks of the diagnostics kernels
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+double splitmix_uniform(uint64_t seed, uint64_t i) {
+    // SplitMix64 (Steele, Lea & Flood 2014): i-th output of the generator
+    // seeded with `seed`, top 53 bits to [0, 1), then to [-1, 1).
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
+}
+
+int mesh_nodes(int n, double stretch, double *x, double *L) {
+    if (n < 1 || !x) return RTLBFS_EINVAL;
+    if (!(stretch > 0.0)) {
+        for (int i = 0; i <= n; ++i) x[i] = i;
+        if (L) *L = n;
+        return RTLBFS_OK;
+    }
+    // Eq. 74 on the unit interval, rescaled so the finest cell has size 1.
+    const double th = std::tanh(stretch);
+    for (int i = 0; i <= n; ++i) x[i] = 0.5 * (th + std::tanh(2.0 * stretch * ((double)i / n - 0.5))) / th;
+    double hmin = 1e300;
+    for (int i = 0; i < n; ++i) hmin = std::min(hmin, x[i + 1] - x[i]);
+    const double len = 1.0 / hmin;
+    for (int i = 0; i <= n; ++i) x[i] *= len;
+    if (L) *L = len;
+    return RTLBFS_OK;
+}
+
+struct Layout {
+    size_t off_U[2], off_w, off_parts, off_red, bytes;
+    int64_t cells;
+    int nparts;
+};
+
+int elem_size(int precision) { return precision == RTLBFS_FP32_DEV ? 4 : 8; }
+
+int step_blocks(const rtlbfs_mesh &m) {
+    if (m.dim == 2) return ((m.n[0] + kTX2 - 1) / kTX2) * ((m.n[1] + kTY2 - 1) / kTY2);
+    return ((m.n[0] + kTX3 - 1) / kTX3) * ((m.n[1] + kTY3 - 1) / kTY3) * ((m.n[2] + kTZ3 - 1) / kTZ3);
+}
+
+int64_t field_stride(int64_t cells) { return (cells + 63) / 64 * 64; }
+
+Layout make_layout(const rtlbfs_mesh &m, int precision) {
+    Layout l{};
+    l.cells = (int64_t)m.n[0] * m.n[1] * (m.dim == 3 ? m.n[2] : 1);
+    const int nf = m.dim + 2;
+    // Fields of one copy are `field_stride` elements apart (a multiple of 64
+    // elements, so every field starts 256-byte aligned).
+    const size_t copy_bytes = (size_t)nf * field_stride(l.cells) * elem_size(precision);
+    size_t off = 0;
+    l.off_U[0] = off;
+    off += copy_bytes;
+    l.off_U[1] = off;
+    off += copy_bytes;
+    l.off_w = off;
+    off += align256(sizeof(double) * (m.n[0] + m.n[1] + (m.dim == 3 ? m.n[2] : 0)));
+    l.nparts = std::max(step_blocks(m), kRedBlocks);
+    l.off_parts = off;
+    off += align256(sizeof(double) * (size_t)l.nparts * 8);
+    l.off_red = off;  // residual sums (8), Nusselt (8), integrals (4), M0 (1), mass-fix sums (4)
+    off += align256(sizeof(double) * 32);
+    l.bytes = off;
+    return l;
+}
+
+}  // namespace
+
+struct rtlbfs_handle {
+    rtlbfs_mesh mesh;
+    rtlbfs_bc bc;
+    rtlbfs_opts opts;
+    Domain dom;
+    Layout lay;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    char *ws = nullptr;
+    bool own_ws = false;
+    int cur = 0;  // which ping-pong copy holds the state
+    int64_t steps = 0;
+    int64_t since_fix = 0;
+    bool res_valid = false;
+    double L = 0, length[3] = {1, 1, 1};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_len = 0;
+    double *host_buf = nullptr;  // pinned scratch for small reads
+    std::string err;
+
+    void *U(int k) { return ws + lay.off_U[k]; }
+    double *parts() { return (double *)(ws + lay.off_parts); }
+    double *red() { return (double *)(ws + lay.off_red); }
+    double *res_out() { return red(); }         // [0..5)
+    double *nu_out() { return red() + 8; }      // [8..16)
+    double *int_out() { return red() + 16; }    // [16..19)
+    double *m0() { return red() + 20; }         // [20]
+    double *fix_out() { return red() + 24; }    // [24..27)
+};
+
+namespace {
+
+thread_local std::string g_create_err;  // detail of the last failed create on this thread
+
+int fail(rtlbfs_t h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    g_create_err = msg;
+    return code;
+}
+
+int hip_fail(rtlbfs_t h, hipError_t e, const char *what) {
+    return fail(h, RTLBFS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, call)                                       \
+    do {                                                       \
+        hipError_t _e = (call);                                \
+        if (_e != hipSuccess) return hip_fail((h), _e, #call); \
+    } while (0)
+
+int heat_axis(const rtlbfs_mesh &m, const rtlbfs_bc &bc) {
+    for (int a = 0; a < m.dim; ++a)
+        if (bc.kind[2 * a] == RTLBFS_WALL_ISOTHERMAL && bc.kind[2 * a + 1] == RTLBFS_WALL_ISOTHERMAL) return a;
+    return -1;
+}
+
+int validate(const rtlbfs_mesh *m, const rtlbfs_bc *bc, const rtlbfs_opts &o, double Ra, double Pr, double Ma,
+             std::string &why) {
+    if (!m || !bc) return why = "mesh or bc is NULL", RTLBFS_EINVAL;
+    if (m->dim != 2 && m->dim != 3) return why = "dim must be 2 or 3", RTLBFS_EINVAL;
+    for (int a = 0; a < m->dim; ++a) {
+        if (m->n[a] < 4) return why = "each axis needs >= 4 cells", RTLBFS_EINVAL;
+        if (m->n[a] > (1 << 20)) return why = "axis too long", RTLBFS_EINVAL;
+        const int k0 = bc->kind[2 * a], k1 = bc->kind[2 * a + 1];
+        for (int k : {k0, k1})
+            if (k != RTLBFS_PERIODIC && k != RTLBFS_WALL_ISOTHERMAL && k != RTLBFS_WALL_ADIABATIC)
+                return why = "unknown boundary kind", RTLBFS_EINVAL;
+        if ((k0 == RTLBFS_PERIODIC) != (k1 == RTLBFS_PERIODIC))
+            return why = "periodic sides must come in pairs", RTLBFS_EINVAL;
+        if (k0 == RTLBFS_PERIODIC && m->stretch[a] > 0.0)
+            return why = "periodic axes must be uniform", RTLBFS_EINVAL;
+        if (!(m->stretch[a] >= 0.0) || m->stretch[a] > 10.0) return why = "stretch out of range", RTLBFS_EINVAL;
+    }
+    if (bc->gravity_axis < -1 || bc->gravity_axis >= m->dim) return why = "gravity_axis out of range", RTLBFS_EINVAL;
+    if (o.precision != RTLBFS_FP64_PLAIN && o.precision != RTLBFS_FP32_DEV && o.precision != RTLBFS_FP64_DEV)
+        return why = "unknown precision", RTLBFS_EINVAL;
+    if (o.phys_given) {
+        if (!(o.nu > 0.0) || !(o.chi > 0.0) || !(o.beta_g >= 0.0)) return why = "nu, chi > 0, beta_g >= 0", RTLBFS_EINVAL;
+    } else {
+        if (!(Ra > 0.0) || !(Pr > 0.0)) return why = "Ra and Pr must be > 0", RTLBFS_EINVAL;
+        if (!(Ma > 0.0) || Ma > 0.3) return why = "Ma must be in (0, 0.3]", RTLBFS_EINVAL;
+    }
+    if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return why = "dtl and dt must be >= 0", RTLBFS_EINVAL;
+    if (o.init != RTLBFS_INIT_REST && o.init != RTLBFS_INIT_CONDUCTION) return why = "unknown init", RTLBFS_EINVAL;
+    return RTLBFS_OK;
+}
+
+template <typename R>
+void to_storage(const std::vector<double> &src, std::vector<char> &dst) {
+    dst.resize(src.size() * sizeof(R));
+    R *p = (R *)dst.data();
+    for (size_t i = 0; i < src.size(); ++i) p[i] = (R)src[i];
+}
+
+template <typename R>
+void from_storage(const char *src, size_t n, double *dst) {
+    const R *p = (const R *)src;
+    for (size_t i = 0; i < n; ++i) dst[i] = (double)p[i];
+}
+
+// Upload the state given as primitives (rho, u axis-major, T' = T - T0).
+int upload_prims(rtlbfs_t h, const double *rho, const double *u, const double *Tdev) {
+    const int64_t N = h->lay.cells;
+    const int D = h->mesh.dim, nf = D + 2;
+    const bool dev = h->opts.precision != RTLBFS_FP64_PLAIN;
+    std::vector<double> f((size_t)N);
+    std::vector<char> buf;
+    const size_t field_bytes = (size_t)h->dom.fstride * elem_size(h->opts.precision);
+    for (int k = 0; k < nf; ++k) {
+        for (int64_t c = 0; c < N; ++c) {
+            if (k == 0) f[c] = dev ? rho[c] - 1.0 : rho[c];
+            else if (k <= D) f[c] = rho[c] * u[(int64_t)(k - 1) * N + c];
+            else f[c] = dev ? rho[c] * Tdev[c] : rho[c] * (kT0 + Tdev[c]);
+        }
+        if (h->opts.precision == RTLBFS_FP32_DEV) to_storage<float>(f, buf);
+        else to_storage<double>(f, buf);
+        HIP_TRY(h, hipMemcpyAsync((char *)h->U(h->cur) + k * field_bytes, buf.data(), buf.size(),
+                                  hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    h->res_valid = false;
+    return RTLBFS_OK;
+}
+
+int read_stored(rtlbfs_t h, int k, std::vector<double> &out) {
+    const int64_t N = h->lay.cells;
+    const size_t es = elem_size(h->opts.precision);
+    const size_t field_bytes = (size_t)h->dom.fstride * es;
+    std::vector<char> buf((size_t)N * es);
+    HIP_TRY(h, hipMemcpyAsync(buf.data(), (char *)h->U(h->cur) + k * field_bytes, buf.size(), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out.resize((size_t)N);
+    if (es == 4) from_storage<float>(buf.data(), (size_t)N, out.data());
+    else from_storage<double>(buf.data(), (size_t)N, out.data());
+    return RTLBFS_OK;
+}
+
+template <typename R, bool DEV>
+hipError_t launch_step(rtlbfs_t h, bool res, hipStream_t s) {
+    const Domain &d = h->dom;
+    const R *Uin = (const R *)h->U(h->cur);
+    R *Uout = (R *)h->U(h->cur ^ 1);
+    if (d.dim == 2) {
+        dim3 grid((d.n[0] + kTX2 - 1) / kTX2, (d.n[1] + kTY2 - 1) / kTY2);
+        if (res) k_step2d<R, DEV, kTX2, kTY2, true><<<grid, 256, 0, s>>>(d, Uin, Uout, h->parts());
+        else k_step2d<R, DEV, kTX2, kTY2, false><<<grid, 256, 0, s>>>(d, Uin, Uout, h->parts());
+    } else {
+        dim3 grid((d.n[0] + kTX3 - 1) / kTX3, (d.n[1] + kTY3 - 1) / kTY3, (d.n[2] + kTZ3 - 1) / kTZ3);
+        constexpr int nt = kTX3 * kTY3 * kTZ3;
+        if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
+        else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
+    }
+    return hipGetLastError();
+}
+
+hipError_t enqueue_step(rtlbfs_t h, bool res, hipStream_t s) {
+    hipError_t e;
+    switch (h->opts.precision) {
+        case RTLBFS_FP64_PLAIN: e = launch_step<double, false>(h, res, s); break;
+        case RTLBFS_FP64_DEV: e = launch_step<double, true>(h, res, s); break;
+        default: e = launch_step<float, true>(h, res, s); break;
+    }
+    if (e != hipSuccess) return e;
+    h->cur ^= 1;
+    if (res) {
+        k_finalize_sum<kPartials><<<1, 256, 0, s>>>(h->parts(), step_blocks(h->mesh), h->res_out());
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t enqueue_integrals(rtlbfs_t h, double *out, hipStream_t s) {
+    const Domain &d = h->dom;
+    switch (h->opts.precision) {
+        case RTLBFS_FP64_PLAIN:
+            k_integrals<double, false><<<kRedBlocks, 256, 0, s>>>(d, (const double *)h->U(h->cur), h->parts());
+            break;
+        case RTLBFS_FP64_DEV:
+            k_integrals<double, true><<<kRedBlocks, 256, 0, s>>>(d, (const double *)h->U(h->cur), h->parts());
+            break;
+        default:
+            k_integrals<float, true><<<kRedBlocks, 256, 0, s>>>(d, (const float *)h->U(h->cur), h->parts());
+            break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finalize_sum<kIntParts><<<1, 256, 0, s>>>(h->parts(), kRedBlocks, out);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_mass_fix(rtlbfs_t h, hipStream_t s) {
+    hipError_t e = enqueue_integrals(h, h->fix_out(), s);
+    if (e != hipSuccess) return e;
+    k_mass_fix<float><<<kRedBlocks, 256, 0, s>>>((float *)h->U(h->cur), h->lay.cells, h->fix_out(), h->m0());
+    return hipGetLastError();
+}
+
+// Capture `len` steps (the last with the residual) starting from copy `par`.
+int capture_graph(rtlbfs_t h, int par, int len) {
+    const int saved = h->cur;
+    h->cur = par;
+    hipGraph_t g = nullptr;
+    HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < len && e == hipSuccess; ++k) e = enqueue_step(h, k == len - 1, h->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    h->cur = saved;
+    if (e != hipSuccess) return hip_fail(h, e, "step launch during capture");
+    if (e2 != hipSuccess) return hip_fail(h, e2, "hipStreamEndCapture");
+    hipError_t e3 = hipGraphInstantiate(&h->graph[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return hip_fail(h, e3, "hipGraphInstantiate");
+    return RTLBFS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- C ABI --
+
+extern "C" {
+
+const char *rtlbfs_strerror(int code) {
+    switch (code) {
+        case RTLBFS_OK: return "ok";
+        case RTLBFS_EINVAL: return "invalid argument";
+        case RTLBFS_ENOMEM: return "out of device memory or workspace too small";
+        case RTLBFS_EDEVICE: return "HIP runtime error";
+        case RTLBFS_EDIVERGED: return "solution diverged (NaN/Inf or Mach > 0.5)";
+        case RTLBFS_EUNSUPPORTED: return "unsupported request";
+        case RTLBFS_ESTATE: return "invalid call order";
+        default: return "unknown status";
+    }
+}
+
+const char *rtlbfs_last_error(rtlbfs_t h) { return h ? h->err.c_str() : g_create_err.c_str(); }
+
+int rtlbfs_opts_init(rtlbfs_opts *o) {
+    if (!o) return RTLBFS_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = RTLBFS_FP64_PLAIN;
+    o->residual_every = 100;
+    o->mass_fix_every = 1000;
+    o->graph_steps = 0;
+    return RTLBFS_OK;
+}
+
+int rtlbfs_mesh_nodes(int n, double stretch, double *host_x, double *L) { return mesh_nodes(n, stretch, host_x, L); }
+
+size_t rtlbfs_workspace_bytes(const rtlbfs_mesh *mesh, const rtlbfs_opts *opts) {
+    if (!mesh || (mesh->dim != 2 && mesh->dim != 3)) return 0;
+    for (int a = 0; a < mesh->dim; ++a)
+        if (mesh->n[a] < 4) return 0;
+    rtlbfs_opts o;
+    if (opts) o = *opts;
+    else rtlbfs_opts_init(&o);
+    return make_layout(*mesh, o.precision).bytes;
+}
+
+int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, const rtlbfs_bc *bc,
+                  const rtlbfs_opts *opts, void *hip_stream, void *workspace, size_t ws_bytes, rtlbfs_t *out) {
+    if (!out) return RTLBFS_EINVAL;
+    *out = nullptr;
+    rtlbfs_opts o;
+    if (opts) o = *opts;
+    else rtlbfs_opts_init(&o);
+    std::string why;
+    g_create_err.clear();
+    int rc = validate(mesh, bc, o, Ra, Pr, Ma, why);
+    if (rc != RTLBFS_OK) {
+        g_create_err = why;
+        return rc;
+    }
+    rtlbfs_t h = new (std::nothrow) rtlbfs_handle();
+    if (!h) return RTLBFS_ENOMEM;
+    h->mesh = *mesh;
+    if (h->mesh.dim == 2) {
+        h->mesh.n[2] = 1;
+        h->mesh.stretch[2] = 0.0;
+    }
+    h->bc = *bc;
+    if (o.residual_every <= 0) o.residual_every = 100;
+    if (o.mass_fix_every == 0) o.mass_fix_every = 1000;
+    h->opts = o;
+    h->stream = (hipStream_t)hip_stream;
+    h->lay = make_layout(h->mesh, o.precision);
+
+    // Mesh and lengths.
+    const int D = h->mesh.dim;
+    std::vector<double> widths;
+    for (int a = 0; a < D; ++a) {
+        std::vector<double> x(h->mesh.n[a] + 1);
+        mesh_nodes(h->mesh.n[a], h->mesh.stretch[a], x.data(), &h->length[a]);
+        for (int i = 0; i < h->mesh.n[a]; ++i) widths.push_back(x[i + 1] - x[i]);
+    }
+    const int ha = heat_axis(h->mesh, *bc);
+    const int la = ha >= 0 ? ha : (bc->gravity_axis >= 0 ? bc->gravity_axis : 0);
+    h->L = h->length[la];
+
+    // Eq. 63 with V_c = Ma, dT = 1 (or the given physics), Eqs. 9-10.
+    double nu, chi, bg;
+    if (o.phys_given) {
+        nu = o.nu;
+        chi = o.chi;
+        bg = o.beta_g;
+    } else {
+        nu = Ma * h->L * std::sqrt(Pr / Ra);
+        chi = nu / Pr;
+        bg = Ma * Ma / h->L;
+    }
+    const double dtl = o.dtl > 0.0 ? o.dtl : 1.0;
+    const double dt = o.dt > 0.0 ? o.dt : std::min(0.5, 0.15 / std::max(nu, chi));
+    h->opts.dtl = dtl;
+    h->opts.dt = dt;
+    h->opts.nu = nu;
+    h->opts.chi = chi;
+    h->opts.beta_g = bg;
+
+    Domain &d = h->dom;
+    std::memset(&d, 0, sizeof(d));
+    d.dim = D;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = a < D ? h->mesh.n[a] : 1;
+        d.periodic[a] = a < D ? bc->kind[2 * a] == RTLBFS_PERIODIC : 1;
+    }
+    const bool dev = o.precision != RTLBFS_FP64_PLAIN;
+    for (int s = 0; s < 6; ++s) {
+        d.kind[s] = s < 2 * D ? bc->kind[s] : RTLBFS_PERIODIC;
+        d.Tw[s] = dev ? bc->Tdev[s] : kT0 + bc->Tdev[s];
+    }
+    d.gaxis = bc->gravity_axis;
+    d.force_pred = o.buoyancy_update_only ? 0 : 1;
+    d.nu = nu;
+    d.chi = chi;
+    d.bg = bg;
+    d.dtl = dtl;
+    d.dt = dt;
+    d.tau_f = 0.5 + nu / (kCs2 * dtl);
+    d.tau_g = 0.5 + chi / (kCs2 * dtl);
+    d.cells = h->lay.cells;
+    d.fstride = field_stride(d.cells);
+
+    // Workspace.
+    if (workspace) {
+        if (ws_bytes < h->lay.bytes) {
+            delete h;
+            g_create_err = "workspace smaller than rtlbfs_workspace_bytes()";
+            return RTLBFS_ENOMEM;
+        }
+        h->ws = (char *)workspace;
+    } else {
+        hipError_t e = hipMalloc((void **)&h->ws, h->lay.bytes);
+        if (e != hipSuccess) {
+            delete h;
+            g_create_err = "hipMalloc of the workspace failed";
+            return RTLBFS_ENOMEM;
+        }
+        h->own_ws = true;
+    }
+    for (int a = 0; a < D; ++a) d.w[a] = nullptr;
+    {
+        double *wdev = (double *)(h->ws + h->lay.off_w);
+        size_t off = 0;
+        for (int a = 0; a < D; ++a) {
+            d.w[a] = wdev + off;
+            off += h->mesh.n[a];
+        }
+        hipError_t e = hipMemcpy(wdev, widths.data(), widths.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            int r2 = hip_fail(h, e, "upload widths");
+            rtlbfs_destroy(h);
+            return r2;
+        }
+    }
+    {
+        hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_buf, 64 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            int r2 = hip_fail(h, e, "capture stream / pinned buffer");
+            rtlbfs_destroy(h);
+            return r2;
+        }
+    }
+
+    // Seeded initial state (absolute primitives on the host, then storage).
+    const int64_t N = h->lay.cells;
+    std::vector<double> centre;  // cell centres of the heat axis
+    if (ha >= 0) {
+        std::vector<double> x(h->mesh.n[ha] + 1);
+        mesh_nodes(h->mesh.n[ha], h->mesh.stretch[ha], x.data(), nullptr);
+        for (int i = 0; i < h->mesh.n[ha]; ++i) centre.push_back(0.5 * (x[i] + x[i + 1]));
+    }
+    std::vector<double> rho((size_t)N, 1.0), u((size_t)N * D, 0.0), T((size_t)N);
+    for (int64_t c = 0; c < N; ++c) {
+        double Tp = 0.0;
+        if (o.init == RTLBFS_INIT_CONDUCTION && ha >= 0) {
+            const int64_t stride = ha == 0 ? 1 : (ha == 1 ? h->mesh.n[0] : (int64_t)h->mesh.n[0] * h->mesh.n[1]);
+            const int i = (int)((c / stride) % h->mesh.n[ha]);
+            const double xi = centre[i] / h->length[ha];
+            Tp = bc->Tdev[2 * ha] + (bc->Tdev[2 * ha + 1] - bc->Tdev[2 * ha]) * xi;
+        }
+        Tp += o.noise_amp * splitmix_uniform(o.seed, (uint64_t)c);
+        T[c] = Tp;  // deviation T - T0
+    }
+    rc = upload_prims(h, rho.data(), u.data(), T.data());
+    if (rc != RTLBFS_OK) {
+        rtlbfs_destroy(h);
+        return rc;
+    }
+    // Reference mass for the drift correction.
+    {
+        hipError_t e = enqueue_integrals(h, h->int_out(), h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->m0(), h->int_out(), sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) {
+            int r2 = hip_fail(h, e, "initial integrals");
+            rtlbfs_destroy(h);
+            return r2;
+        }
+    }
+    *out = h;
+    return RTLBFS_OK;
+}
+
+int rtlbfs_step(rtlbfs_t h, int64_t n) {
+    if (!h) return RTLBFS_EINVAL;
+    if (n < 0) return fail(h, RTLBFS_EINVAL, "negative step count");
+    const int C = h->opts.residual_every;
+    const bool graphs = h->opts.graph_steps >= 0;
+    while (n > 0) {
+        const int64_t chunk = std::min<int64_t>(n, C);
+        if (graphs && chunk == C) {
+            if (!h->graph[h->cur]) {
+                int rc = capture_graph(h, h->cur, C);
+                if (rc != RTLBFS_OK) return rc;
+            }
+            HIP_TRY(h, hipGraphLaunch(h->graph[h->cur], h->stream));
+            if (C & 1) h->cur ^= 1;
+        } else {
+            for (int64_t k = 0; k < chunk; ++k) {
+                hipError_t e = enqueue_step(h, k == chunk - 1, h->stream);
+                if (e != hipSuccess) return hip_fail(h, e, "step launch");
+            }
+        }
+        n -= chunk;
+        h->steps += chunk;
+        h->since_fix += chunk;
+        h->res_valid = true;
+        if (h->opts.precision == RTLBFS_FP32_DEV && h->opts.mass_fix_every > 0 &&
+            h->since_fix >= h->opts.mass_fix_every) {
+            hipError_t e = enqueue_mass_fix(h, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "mass fix");
+            h->since_fix = 0;
+        }
+    }
+    return RTLBFS_OK;
+}
+
+int rtlbfs_sync(rtlbfs_t h) {
+    if (!h) return RTLBFS_EINVAL;
+    HIP_TRY(h, hipMemcpyAsync(h->host_buf, h->res_out(), kPartials * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (h->res_valid && h->host_buf[4] != 0.0) return fail(h, RTLBFS_EDIVERGED, "NaN/Inf or Mach > 0.5 detected");
+    return RTLBFS_OK;
+}
+
+int rtlbfs_residual(rtlbfs_t h, double *res_u, double *res_T) {
+    if (!h || !res_u || !res_T) return RTLBFS_EINVAL;
+    if (!h->res_valid) return fail(h, RTLBFS_ESTATE, "no residual step yet");
+    int rc = rtlbfs_sync(h);
+    const double *r = h->host_buf;
+    *res_u = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+    *res_T = r[3] != 0.0 ? r[2] / r[3] : 0.0;
+    return rc;
+}
+
+int rtlbfs_nusselt(rtlbfs_t h, rtlbfs_nu *out) {
+    if (!h || !out) return RTLBFS_EINVAL;
+    const int ha = heat_axis(h->mesh, h->bc);
+    if (ha < 0) return fail(h, RTLBFS_EINVAL, "no pair of isothermal walls");
+    const double Tlo = h->bc.Tdev[2 * ha], Thi = h->bc.Tdev[2 * ha + 1];
+    const double dTw = std::fabs(Thi - Tlo);
+    if (dTw == 0.0) return fail(h, RTLBFS_EINVAL, "isothermal walls at equal temperature");
+    const int hot_hi = Thi > Tlo;
+    const Domain &d = h->dom;
+    double *parts = h->parts();
+    switch (h->opts.precision) {
+        case RTLBFS_FP64_PLAIN:
+            k_nusselt<double, false><<<kRedBlocks, 256, 0, h->stream>>>(d, (const double *)h->U(h->cur), ha, hot_hi,
+                                                                        h->length[ha], dTw, parts);
+            break;
+        case RTLBFS_FP64_DEV:
+            k_nusselt<double, true><<<kRedBlocks, 256, 0, h->stream>>>(d, (const double *)h->U(h->cur), ha, hot_hi,
+                                                                       h->length[ha], dTw, parts);
+            break;
+        default:
+            k_nusselt<float, true><<<kRedBlocks, 256, 0, h->stream>>>(d, (const float *)h->U(h->cur), ha, hot_hi,
+                                                                      h->length[ha], dTw, parts);
+            break;
+    }
+    HIP_TRY(h, hipGetLastError());
+    k_nusselt_finalize<<<1, 256, 0, h->stream>>>(parts, kRedBlocks, h->nu_out());
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipMemcpyAsync(h->host_buf + 8, h->nu_out(), 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const double *r = h->host_buf + 8;
+    out->hot_avg = r[0] / r[1];
+    out->cold_avg = r[2] / r[3];
+    out->volume = h->length[ha] / (d.chi * dTw) * r[4] / r[5];
+    out->hot_max = r[6];
+    out->cold_max = r[7];
+    return RTLBFS_OK;
+}
+
+int rtlbfs_integrals(rtlbfs_t h, double out[3]) {
+    if (!h || !out) return RTLBFS_EINVAL;
+    HIP_TRY(h, enqueue_integrals(h, h->int_out(), h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->host_buf + 16, h->int_out(), 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 3; ++k) out[k] = h->host_buf[16 + k];
+    return RTLBFS_OK;
+}
+
+int rtlbfs_get_stored(rtlbfs_t h, int field, double *host_out, size_t count) {
+    if (!h || !host_out) return RTLBFS_EINVAL;
+    if (field < 0 || field > h->mesh.dim + 1) return fail(h, RTLBFS_EINVAL, "field out of range");
+    if (count < (size_t)h->lay.cells) return fail(h, RTLBFS_EINVAL, "count smaller than the cell count");
+    std::vector<double> f;
+    int rc = read_stored(h, field, f);
+    if (rc != RTLBFS_OK) return rc;
+    std::memcpy(host_out, f.data(), f.size() * sizeof(double));
+    return RTLBFS_OK;
+}
+
+int rtlbfs_get_field(rtlbfs_t h, int field, double *host_out, size_t count) {
+    if (!h || !host_out) return RTLBFS_EINVAL;
+    const int D = h->mesh.dim;
+    if (field < 0 || field > D + 1) return fail(h, RTLBFS_EINVAL, "field out of range");
+    if (count < (size_t)h->lay.cells) return fail(h, RTLBFS_EINVAL, "count smaller than the cell count");
+    const bool dev = h->opts.precision != RTLBFS_FP64_PLAIN;
+    std::vector<double> r, f;
+    int rc = read_stored(h, 0, r);
+    if (rc != RTLBFS_OK) return rc;
+    if (field > 0 && (rc = read_stored(h, field, f)) != RTLBFS_OK) return rc;
+    for (int64_t c = 0; c < h->lay.cells; ++c) {
+        const double rho = dev ? 1.0 + r[c] : r[c];
+        if (field == 0) host_out[c] = rho;
+        else if (field <= D) host_out[c] = f[c] / rho;
+        else host_out[c] = f[c] / rho + (dev ? kT0 : 0.0);
+    }
+    return RTLBFS_OK;
+}
+
+int rtlbfs_set_state(rtlbfs_t h, const double *rho, const double *u, const double *T, size_t cells) {
+    if (!h || !rho || !u || !T) return RTLBFS_EINVAL;
+    if (cells != (size_t)h->lay.cells) return fail(h, RTLBFS_EINVAL, "cell count mismatch");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::vector<double> Tdev(cells);
+    for (size_t c = 0; c < cells; ++c) Tdev[c] = T[c] - kT0;
+    int rc = upload_prims(h, rho, u, Tdev.data());
+    if (rc != RTLBFS_OK) return rc;
+    HIP_TRY(h, enqueue_integrals(h, h->int_out(), h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->m0(), h->int_out(), sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->since_fix = 0;
+    return RTLBFS_OK;
+}
+
+int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
+    if (!h || !out) return RTLBFS_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->cells = h->lay.cells;
+    out->steps = h->steps;
+    out->L = h->L;
+    out->nu = h->dom.nu;
+    out->chi = h->dom.chi;
+    out->beta_g = h->dom.bg;
+    out->tau_f = h->dom.tau_f;
+    out->tau_g = h->dom.tau_g;
+    out->dtl = h->dom.dtl;
+    out->dt = h->dom.dt;
+    for (int a = 0; a < 3; ++a) out->length[a] = a < h->mesh.dim ? h->length[a] : 1.0;
+    out->precision = h->opts.precision;
+    if (h->mesh.dim == 2) {
+        out->tile_x = kTX2;
+        out->tile_y = kTY2;
+        out->tile_z = 1;
+    } else {
+        out->tile_x = kTX3;
+        out->tile_y = kTY3;
+        out->tile_z = kTZ3;
+    }
+    return RTLBFS_OK;
+}
+
+int rtlbfs_destroy(rtlbfs_t h) {
+    if (!h) return RTLBFS_OK;
+    if (h->stream || h->cap_stream) (void)hipStreamSynchronize(h->stream);
+    for (int k = 0; k < 2; ++k)
+        if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->host_buf) (void)hipHostFree(h->host_buf);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    delete h;
+    return RTLBFS_OK;
+}
+
+}  // extern "C"

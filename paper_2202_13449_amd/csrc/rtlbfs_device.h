@@ -1,0 +1,264 @@
+// rtlbfs_device.h -- device-side data structures and arithmetic of the RTLBFS
+// step for gfx950 (CDNA4): domain descriptor, FP64 wave/block reductions and
+// the face flux of Sec. 3.2 in 2D and 3D (Lu, Dai & Yu, arXiv 2202.13449).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtlbfs {
+
+constexpr double kCs2 = 1.0 / 3.0;  // c_s^2 = c^2/3 (Eq. 6)
+constexpr double kT0 = 0.5;         // T_ref = (T_h + T_l)/2, T_l = 0, T_h = 1 (Eq. 64)
+constexpr int kPartials = 5;        // residual partial sums per block
+
+enum : int { kPeriodic = 0, kIsothermal = 1, kAdiabatic = 2 };
+
+// One structured domain as the kernels see it.  Lengths in lattice units;
+// Tw is in the storage convention (T - T0 for deviation storage, absolute T
+// for plain storage).
+struct Domain {
+    int dim;
+    int n[3];
+    int periodic[3];
+    int kind[6];
+    double Tw[6];
+    int gaxis;        // buoyancy along +gaxis, -1 none
+    int force_pred;   // 1: buoyancy also in the predicted momentum
+    double nu, chi, bg, dtl, dt, tau_f, tau_g;
+    const double *w[3];  // cell widths per axis (device)
+    int64_t cells;       // number of cells
+    int64_t fstride;     // elements between consecutive fields of one state copy
+};
+
+// ------------------------------------------------------------ reductions --
+
+// Sum over the 64 lanes of a wavefront (butterfly of cross-lane moves).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block-wide sums of K values; the result is valid in thread 0.  `scratch`
+// holds K * (blockDim/64) doubles of shared memory.
+template <int K>
+__device__ inline void block_sums(double (&v)[K], double *scratch) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) scratch[k * nw + wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += scratch[k * nw + w];
+            v[k] = s;
+        }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ face flux --
+
+template <typename R>
+struct Phys {
+    R nu, chi, dtl, tau_f, tau_g, bg;
+    R h, inv2h, invh2, inv4h2;
+};
+
+template <typename R>
+__device__ inline Phys<R> make_phys(const Domain &d) {
+    Phys<R> p;
+    p.nu = (R)d.nu;
+    p.chi = (R)d.chi;
+    p.dtl = (R)d.dtl;
+    p.tau_f = (R)d.tau_f;
+    p.tau_g = (R)d.tau_g;
+    p.bg = (R)d.bg;
+    p.h = (R)d.dtl;  // lattice spacing c * delta-t with c = 1
+    p.inv2h = (R)(1.0 / (2.0 * d.dtl));
+    p.invh2 = (R)(1.0 / (d.dtl * d.dtl));
+    p.inv4h2 = (R)(1.0 / (4.0 * d.dtl * d.dtl));
+    return p;
+}
+
+// One side of a face: cell-centre primitives (r, u_0..u_{D-1}, T) in the
+// face-local frame (axis 0 = face normal n, then the tangents) and their
+// gradients g[k][p] along local axis k.
+template <typename R, int D>
+struct Side {
+    R v[D + 2];
+    R g[D][D + 2];
+};
+
+// Interior-face flux per unit area along +n (Sec. 3.2) for D = 2 (D2Q9 node
+// offsets) or D = 3 (D3Q19 offsets).  DEV selects the deviation storage
+// (r = rho - 1, theta = rho (T - T0)); otherwise r is rho and T absolute.
+// fdir: buoyancy unit vector in the local frame (added as dt * F at the face
+// centre to the predicted momentum).  out = {mass, m_0..m_{D-1}, energy}.
+//
+// The lattice nodes X = x_S + h (a n + b t1 + c t2) take the primitives of
+// Eq. 29: a < 0 from the left cell, a > 0 from the right cell, a = 0 the mean
+// of both; in each column a the value is affine in (b, c).  Every node adds
+// its products to the central-difference accumulators of Eqs. 46-48:
+// D_k f = (f(+k) - f(-k))/2h, D_kk f = (f(+k) - 2 f(0) + f(-k))/h^2,
+// D_kl f = (f(+k+l) - f(+k-l) - f(-k+l) + f(-k-l))/4h^2.
+template <typename R, int D, bool DEV>
+__device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR, const R (&fdir)[D],
+                                 const Phys<R> &ph, R (&out)[D + 2]) {
+    constexpr int NP = D + 2;
+    const R cs2 = (R)kCs2;
+    const R half = (R)0.5;
+    R base[3][NP], slope[3][D][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        base[0][p] = L.v[p] + L.g[0][p] * (dL - ph.h);       // X - x_L = (dL - h) n + ...
+        base[2][p] = Rt.v[p] + Rt.g[0][p] * (ph.h - dR);     // X - x_R = (h - dR) n + ...
+        base[1][p] = half * ((L.v[p] + L.g[0][p] * dL) + (Rt.v[p] - Rt.g[0][p] * dR));
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            slope[0][k][p] = ph.h * L.g[k][p];
+            slope[2][k][p] = ph.h * Rt.g[k][p];
+            slope[1][k][p] = half * (slope[0][k][p] + slope[2][k][p]);
+        }
+    }
+    // Accumulators (local axes a, b):
+    R Dn_m[D], Da_mn[D], lapm[D], gdm[D], divK[D], Dr[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) Dn_m[a] = Da_mn[a] = lapm[a] = gdm[a] = divK[a] = Dr[a] = (R)0;
+    R divm = 0, ddK = 0, lapr = 0, divq = 0, lape = 0, Dne = 0;
+    R r0 = 0, e0 = 0, T0n = 0, m0[D], K0n[D], q0n = 0;
+    const R w1 = ph.inv2h, w2 = ph.invh2, w4 = ph.inv4h2;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+            for (int c = -1; c <= 1; ++c) {
+                if (D == 2 && c != 0) continue;
+                if (abs(a) + abs(b) + abs(c) > 2) continue;  // D3Q19 has no corner nodes
+                const int o[3] = {a, b, c};
+                R v[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    R x = base[a + 1][p];
+#pragma unroll
+                    for (int k = 1; k < D; ++k)
+                        if (o[k] != 0) x += (R)o[k] * slope[a + 1][k][p];
+                    v[p] = x;
+                }
+                const R rv = v[0];
+                const R rho = DEV ? (R)1 + rv : rv;
+                R m[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) m[k] = rho * v[1 + k];
+                const R e = rho * v[D + 1];
+                const int nz = (a != 0) + (b != 0) + (c != 0);
+                if (nz == 0) {
+                    r0 = rv;
+                    e0 = e;
+                    T0n = v[D + 1];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        m0[k] = m[k];
+                        K0n[k] = m[k] * v[1];
+                        lapm[k] -= (R)(2 * D) * w2 * m[k];
+                        gdm[k] -= (R)2 * w2 * m[k];
+                        ddK -= (R)2 * w2 * m[k] * v[1 + k];
+                    }
+                    q0n = e * v[1];
+                    lapr -= (R)(2 * D) * w2 * rv;
+                    lape -= (R)(2 * D) * w2 * e;
+                } else if (nz == 1) {
+                    const int k = a != 0 ? 0 : (b != 0 ? 1 : 2);
+                    const R s1 = (R)o[k] * w1;
+                    if (k == 0) {
+#pragma unroll
+                        for (int q = 0; q < D; ++q) Dn_m[q] += s1 * m[q];
+                        Dne += s1 * e;
+                    }
+                    Da_mn[k] += s1 * m[0];
+                    divm += s1 * m[k];
+#pragma unroll
+                    for (int q = 0; q < D; ++q) {
+                        lapm[q] += w2 * m[q];
+                        divK[q] += s1 * m[q] * v[1 + k];  // D_k (rho u_q u_k)
+                    }
+                    gdm[k] += w2 * m[k];
+                    ddK += w2 * m[k] * v[1 + k];
+                    Dr[k] += s1 * rv;
+                    lapr += w2 * rv;
+                    divq += s1 * e * v[1 + k];
+                    lape += w2 * e;
+                } else {
+                    const int k = a != 0 ? 0 : 1;
+                    const int l = c != 0 ? 2 : 1;
+                    const R s4 = (R)(o[k] * o[l]) * w4;
+                    gdm[k] += s4 * m[l];
+                    gdm[l] += s4 * m[k];
+                    ddK += (R)2 * s4 * m[k] * v[1 + l];
+                }
+            }
+    const R dt = ph.dtl, dt2h = half * ph.dtl * ph.dtl;
+    const R rho0 = DEV ? (R)1 + r0 : r0;
+    // Buoyancy at the face centre (Eq. 64).
+    const R Fb = ph.bg * rho0 * (DEV ? T0n : T0n - (R)kT0);
+    // Eqs. 46-48 as increments over the face-centre values.
+    const R dr = -dt * divm + dt2h * (ddK + cs2 * lapr);
+    R dm[D], ms[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        dm[q] = -dt * (divK[q] + cs2 * Dr[q]) + cs2 * dt2h * (lapm[q] + (R)2 * gdm[q]) + dt * fdir[q] * Fb;
+        ms[q] = m0[q] + dm[q];
+    }
+    const R de = -dt * divq + cs2 * dt2h * lape;
+    const R rhos = rho0 + dr, es = e0 + de;
+    const R inv_rhos = (R)1 / rhos;
+    // Eqs. 57-59.
+    out[0] = ms[0];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        R f = K0n[q] - ph.nu * (Dn_m[q] + Da_mn[q]) - (ph.tau_f - (R)1.5) * (ms[q] * ms[0] * inv_rhos - K0n[q]);
+        if (q == 0) f += cs2 * r0 - ph.nu * divm - (ph.tau_f - (R)1.5) * cs2 * dr;
+        out[1 + q] = f;
+    }
+    R fe = q0n - ph.chi * Dne - (ph.tau_g - (R)1.5) * (ms[0] * es * inv_rhos - q0n);
+    if (DEV) {
+        // theta = e - T0 rho is advanced with Q - T0 P; e* = T0 rho_e* + theta*
+        // with rho_e* - rho* = -dt^2/2 d_a d_b (rho u_a u_b).
+        fe += (R)kT0 * (-(ph.tau_g - half) * dm[0] - ph.chi * Dr[0] + (ph.tau_g - (R)1.5) * ms[0] * dt2h * ddK * inv_rhos);
+    }
+    out[D + 1] = fe;
+}
+
+// Wall flux per unit area along +axis for the cell P next to a no-slip wall
+// (outward normal sgn * e_axis, centre-to-wall distance d): no mass flux,
+// pressure c_s^2 r on the normal, one-sided viscous stress with
+// V_n = -3 m_n/d and V_t = -m_t/d, and for an isothermal wall the one-sided
+// conduction -chi (rho T_w - e)/d.  m: momentum in the local frame (m[0]
+// along the wall normal).
+template <typename R, int D, bool DEV>
+__device__ inline void wall_flux(R rP, const R (&m)[D], R eP, R sgn, R d, bool iso, R Tw, const Phys<R> &ph,
+                                 R (&out)[D + 2]) {
+    const R rho = DEV ? (R)1 + rP : rP;
+    const R inv_d = (R)1 / d;
+    out[0] = (R)0;
+    out[1] = (R)kCs2 * rP + sgn * (R)3 * ph.nu * m[0] * inv_d;
+#pragma unroll
+    for (int q = 1; q < D; ++q) out[1 + q] = sgn * ph.nu * m[q] * inv_d;
+    out[D + 1] = iso ? -sgn * ph.chi * (rho * Tw - eP) * inv_d : (R)0;
+}
+
+__device__ inline int wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+}  // namespace rtlbfs

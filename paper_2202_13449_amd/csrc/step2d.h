@@ -1,0 +1,226 @@
+// step2d.h -- one fused RTLBFS step over a TX x TY tile of a 2D domain.
+//
+// Phases, each separated by a workgroup barrier, all through LDS:
+//   1. load the state of the tile plus a 2-cell halo and convert it to
+//      primitives (r or rho, u, v, T or T');
+//   2. Eq. 55 gradients (Eq. 56 face values, wall values on walls) for the
+//      tile plus a 1-cell halo;
+//   3. every face of the tile once: interior / periodic faces by the lattice
+//      predictor-corrector, wall faces by the wall closure; area-weighted
+//      fluxes go to LDS and are shared by the two cells of the face;
+//   4. divergence, Boussinesq source, forward-Euler update (Eqs. 57-59, 64),
+//      and on residual steps the FP64 partial sums of Eq. 65.
+#pragma once
+
+#include "rtlbfs_device.h"
+
+namespace rtlbfs {
+
+template <typename R, bool DEV, int TX, int TY, bool RES>
+__device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, const R *__restrict__ Uin,
+                                             R *__restrict__ Uout, double *__restrict__ part) {
+    constexpr int PX = TX + 4, PY = TY + 4;  // primitives with a 2-cell halo
+    constexpr int GX = TX + 2, GY = TY + 2;  // gradients with a 1-cell halo
+    __shared__ R sp[4][PY][PX];
+    __shared__ R sg[4][2][GY][GX];
+    __shared__ R sfx[4][TY][TX + 1];
+    __shared__ R sfy[4][TY + 1][TX];
+    __shared__ double sred[kPartials * 16];
+
+    const int nx = d.n[0], ny = d.n[1];
+    const int64_t N = d.fstride;
+    const bool px = d.periodic[0], py = d.periodic[1];
+    const double *__restrict__ wx = d.w[0];
+    const double *__restrict__ wy = d.w[1];
+    const Phys<R> ph = make_phys<R>(d);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+
+    // Phase 1: load + primitives.
+    for (int q = tid; q < PX * PY; q += nthr) {
+        const int li = q % PX, lj = q / PX;
+        int gi = i0 - 2 + li, gj = j0 - 2 + lj;
+        if (px) gi = wrap(gi, nx);
+        if (py) gj = wrap(gj, ny);
+        if (gi < 0 || gi >= nx || gj < 0 || gj >= ny) continue;  // outside a wall: never read
+        const int64_t c = (int64_t)gj * nx + gi;
+        const R r = Uin[c], mx = Uin[N + c], my = Uin[2 * N + c], e = Uin[3 * N + c];
+        const R inv_rho = (R)1 / (DEV ? (R)1 + r : r);
+        sp[0][lj][li] = r;
+        sp[1][lj][li] = mx * inv_rho;
+        sp[2][lj][li] = my * inv_rho;
+        sp[3][lj][li] = e * inv_rho;
+    }
+    __syncthreads();
+
+    // Phase 2: gradients, (phi_hi - phi_lo) / width with Eq. 56 face values.
+    for (int q = tid; q < GX * GY; q += nthr) {
+        const int li = q % GX, lj = q / GX;
+        int gi = i0 - 1 + li, gj = j0 - 1 + lj;
+        if (px) gi = wrap(gi, nx);
+        if (py) gj = wrap(gj, ny);
+        if (gi < 0 || gi >= nx || gj < 0 || gj >= ny) continue;
+        const int ci = li + 1, cj = lj + 1;  // position in sp
+        const R wP = (R)wx[gi], hP = (R)wy[gj];
+        const bool wall_w = !px && gi == 0, wall_e = !px && gi == nx - 1;
+        const bool wall_s = !py && gj == 0, wall_n = !py && gj == ny - 1;
+        const R ww = wall_w ? (R)0 : (R)wx[px ? wrap(gi - 1, nx) : gi - 1];
+        const R we = wall_e ? (R)0 : (R)wx[px ? wrap(gi + 1, nx) : gi + 1];
+        const R hs = wall_s ? (R)0 : (R)wy[py ? wrap(gj - 1, ny) : gj - 1];
+        const R hn = wall_n ? (R)0 : (R)wy[py ? wrap(gj + 1, ny) : gj + 1];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const R vP = sp[p][cj][ci];
+            // wall face values: r_S = r_P, u_S = 0, T_S = T_w (isothermal) or T_P
+            auto wallv = [&](int side) -> R {
+                if (p == 0) return vP;
+                if (p < 3) return (R)0;
+                return d.kind[side] == kIsothermal ? (R)d.Tw[side] : vP;
+            };
+            const R fw = wall_w ? wallv(0) : (vP * ww + sp[p][cj][ci - 1] * wP) / (wP + ww);
+            const R fe = wall_e ? wallv(1) : (vP * we + sp[p][cj][ci + 1] * wP) / (wP + we);
+            const R fs = wall_s ? wallv(2) : (vP * hs + sp[p][cj - 1][ci] * hP) / (hP + hs);
+            const R fnn = wall_n ? wallv(3) : (vP * hn + sp[p][cj + 1][ci] * hP) / (hP + hn);
+            sg[p][0][lj][li] = (fe - fw) / wP;
+            sg[p][1][lj][li] = (fnn - fs) / hP;
+        }
+    }
+    __syncthreads();
+
+    // Phase 3: faces.  x-faces: (TX+1) x TY; y-faces: TX x (TY+1).
+    constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1);
+    for (int q = tid; q < NFX + NFY; q += nthr) {
+        R F[4];
+        if (q < NFX) {
+            const int lf = q % (TX + 1), lr = q / (TX + 1);
+            const int gf = i0 + lf, gj = j0 + lr;
+            if (gj >= ny || gf > nx) continue;
+            const R area = (R)wy[gj];
+            if (!px && (gf == 0 || gf == nx)) {
+                const int side = gf == 0 ? 0 : 1;
+                const int ci = gf == 0 ? lf + 2 : lf + 1;  // the wall cell in sp
+                const R sgn = gf == 0 ? (R)-1 : (R)1;
+                const R rP = sp[0][lr + 2][ci];
+                const R rho = DEV ? (R)1 + rP : rP;
+                const R d_w = (R)0.5 * (R)wx[gf == 0 ? 0 : nx - 1];
+                const R mloc[2] = {rho * sp[1][lr + 2][ci], rho * sp[2][lr + 2][ci]};
+                wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][lr + 2][ci], sgn, d_w, d.kind[side] == kIsothermal,
+                                     (R)d.Tw[side], ph, F);
+            } else {
+                Side<R, 2> A, B;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    // normal = x, tangent = y: (r, u_n = u, u_t = v, T)
+                    A.v[p] = sp[p][lr + 2][lf + 1];
+                    B.v[p] = sp[p][lr + 2][lf + 2];
+                    A.g[0][p] = sg[p][0][lr + 1][lf];
+                    A.g[1][p] = sg[p][1][lr + 1][lf];
+                    B.g[0][p] = sg[p][0][lr + 1][lf + 1];
+                    B.g[1][p] = sg[p][1][lr + 1][lf + 1];
+                }
+                const R dL = (R)0.5 * (R)wx[px ? wrap(gf - 1, nx) : gf - 1];
+                const R dR = (R)0.5 * (R)wx[px ? wrap(gf, nx) : gf];
+                const R fdir[2] = {(d.force_pred && d.gaxis == 0) ? (R)1 : (R)0,
+                                   (d.force_pred && d.gaxis == 1) ? (R)1 : (R)0};
+                face_flux<R, 2, DEV>(A, B, dL, dR, fdir, ph, F);
+            }
+            sfx[0][lr][lf] = F[0] * area;
+            sfx[1][lr][lf] = F[1] * area;
+            sfx[2][lr][lf] = F[2] * area;
+            sfx[3][lr][lf] = F[3] * area;
+        } else {
+            const int qq = q - NFX;
+            const int lc = qq % TX, lf = qq / TX;
+            const int gi = i0 + lc, gf = j0 + lf;
+            if (gi >= nx || gf > ny) continue;
+            const R area = (R)wx[gi];
+            R G[4];
+            if (!py && (gf == 0 || gf == ny)) {
+                const int side = gf == 0 ? 2 : 3;
+                const int cj = gf == 0 ? lf + 2 : lf + 1;
+                const R sgn = gf == 0 ? (R)-1 : (R)1;
+                const R rP = sp[0][cj][lc + 2];
+                const R rho = DEV ? (R)1 + rP : rP;
+                const R d_w = (R)0.5 * (R)wy[gf == 0 ? 0 : ny - 1];
+                // normal = y: m_a = m_y, m_b = m_x
+                const R mloc[2] = {rho * sp[2][cj][lc + 2], rho * sp[1][cj][lc + 2]};
+                wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][cj][lc + 2], sgn, d_w, d.kind[side] == kIsothermal,
+                                     (R)d.Tw[side], ph, G);
+            } else {
+                Side<R, 2> A, B;
+                // normal = y, tangent = x: (r, u_n = v, u_t = u, T)
+                const int perm[4] = {0, 2, 1, 3};
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const int pp = perm[p];
+                    A.v[p] = sp[pp][lf + 1][lc + 2];
+                    B.v[p] = sp[pp][lf + 2][lc + 2];
+                    A.g[0][p] = sg[pp][1][lf][lc + 1];
+                    A.g[1][p] = sg[pp][0][lf][lc + 1];
+                    B.g[0][p] = sg[pp][1][lf + 1][lc + 1];
+                    B.g[1][p] = sg[pp][0][lf + 1][lc + 1];
+                }
+                const R dL = (R)0.5 * (R)wy[py ? wrap(gf - 1, ny) : gf - 1];
+                const R dR = (R)0.5 * (R)wy[py ? wrap(gf, ny) : gf];
+                const R fdir[2] = {(d.force_pred && d.gaxis == 1) ? (R)1 : (R)0,
+                                   (d.force_pred && d.gaxis == 0) ? (R)1 : (R)0};
+                face_flux<R, 2, DEV>(A, B, dL, dR, fdir, ph, G);
+            }
+            // back to global components: (mass, m_x = m_t, m_y = m_n, energy)
+            F[0] = G[0];
+            F[1] = G[2];
+            F[2] = G[1];
+            F[3] = G[3];
+            sfy[0][lf][lc] = F[0] * area;
+            sfy[1][lf][lc] = F[1] * area;
+            sfy[2][lf][lc] = F[2] * area;
+            sfy[3][lf][lc] = F[3] * area;
+        }
+    }
+    __syncthreads();
+
+    // Phase 4: update.
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const R dtR = (R)d.dt;
+    for (int q = tid; q < TX * TY; q += nthr) {
+        const int lc = q % TX, lr = q / TX;
+        const int gi = i0 + lc, gj = j0 + lr;
+        if (gi >= nx || gj >= ny) continue;
+        const int64_t c = (int64_t)gj * nx + gi;
+        const R dt_dV = dtR / ((R)wx[gi] * (R)wy[gj]);
+        R Un[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const R div = (sfx[f][lr][lc] - sfx[f][lr][lc + 1]) + (sfy[f][lr][lc] - sfy[f][lr + 1][lc]);
+            Un[f] = Uin[f * N + c] + dt_dV * div;
+        }
+        const R rP = sp[0][lr + 2][lc + 2];
+        const R rhoP = DEV ? (R)1 + rP : rP;
+        const R TP = sp[3][lr + 2][lc + 2];
+        if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) Uout[f * N + c] = Un[f];
+        if (RES) {
+            const double rn = (double)Un[0];
+            const double rhon = DEV ? 1.0 + rn : rn;
+            const double un = (double)Un[1] / rhon, vn = (double)Un[2] / rhon;
+            const double Tn = (double)Un[3] / rhon + (DEV ? kT0 : 0.0);
+            const double uo = (double)sp[1][lr + 2][lc + 2], vo = (double)sp[2][lr + 2][lc + 2];
+            const double To = (double)TP + (DEV ? kT0 : 0.0);
+            const double an = sqrt(un * un + vn * vn), ao = sqrt(uo * uo + vo * vo);
+            acc[0] += fabs(an - ao);
+            acc[1] += an;
+            acc[2] += fabs(Tn - To);
+            acc[3] += Tn;
+            // divergence guard: NaN/Inf or local Mach |u|/c_s > 0.5
+            const bool ok = (an * an < 0.25 * kCs2) && (Tn == Tn) && (fabs(Tn) < 1e30);
+            acc[4] += ok ? 0.0 : 1.0;
+        }
+    }
+    if (RES) {
+        block_sums<kPartials>(acc, sred);
+        if (tid == 0)
+            for (int k = 0; k < kPartials; ++k) part[k] = acc[k];
+    }
+}
+
+}  // namespace rtlbfs

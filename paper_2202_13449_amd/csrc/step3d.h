@@ -1,0 +1,244 @@
+// step3d.h -- one fused RTLBFS step over a TX x TY x TZ tile of a 3D domain
+// (D3Q19 face lattice).  Same phases as the 2D tile: LDS-staged primitives
+// with a 2-cell halo, Eq. 55 gradients with a 1-cell halo, every face of the
+// tile once (lattice predictor-corrector or wall closure) into LDS, then the
+// divergence, buoyancy and forward-Euler update with optional FP64 Eq. 65
+// partial sums.
+#pragma once
+
+#include "rtlbfs_device.h"
+
+namespace rtlbfs {
+
+template <int TX, int TY, int TZ>
+struct Tile3 {
+    static constexpr int PX = TX + 4, PY = TY + 4, PZ = TZ + 4;
+    static constexpr int GX = TX + 2, GY = TY + 2, GZ = TZ + 2;
+    static constexpr int NP = PX * PY * PZ;
+    static constexpr int NG = GX * GY * GZ;
+    // faces normal to axis a: (T[a] + 1) along a, T elsewhere
+    static constexpr int NF0 = (TX + 1) * TY * TZ, NF1 = TX * (TY + 1) * TZ, NF2 = TX * TY * (TZ + 1);
+    __device__ static int pidx(int x, int y, int z) { return (z * PY + y) * PX + x; }  // cell at tile coords - 2
+    __device__ static int gidx(int x, int y, int z) { return (z * GY + y) * GX + x; }  // cell at tile coords - 1
+};
+
+template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
+__device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, int k0, const R *__restrict__ Uin,
+                                             R *__restrict__ Uout, double *__restrict__ part) {
+    using TL = Tile3<TX, TY, TZ>;
+    constexpr int NPRIM = 5;
+    __shared__ R sp[NPRIM][TL::NP];
+    __shared__ R sg[NPRIM][3][TL::NG];
+    __shared__ R sf0[NPRIM][TL::NF0];
+    __shared__ R sf1[NPRIM][TL::NF1];
+    __shared__ R sf2[NPRIM][TL::NF2];
+    __shared__ double sred[kPartials * 16];
+
+    const int n[3] = {d.n[0], d.n[1], d.n[2]};
+    const int org[3] = {i0, j0, k0};
+    const int64_t N = d.fstride;
+    const Phys<R> ph = make_phys<R>(d);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    auto gcell = [&](int c, int a, bool &inside) -> int {  // global index along a, wrapped if periodic
+        if (d.periodic[a]) c = wrap(c, n[a]);
+        inside = c >= 0 && c < n[a];
+        return c;
+    };
+
+    // Phase 1: load + primitives.
+    for (int q = tid; q < TL::NP; q += nthr) {
+        const int lx = q % TL::PX, ly = (q / TL::PX) % TL::PY, lz = q / (TL::PX * TL::PY);
+        bool in0, in1, in2;
+        const int gx = gcell(i0 - 2 + lx, 0, in0), gy = gcell(j0 - 2 + ly, 1, in1), gz = gcell(k0 - 2 + lz, 2, in2);
+        if (!(in0 && in1 && in2)) continue;
+        const int64_t c = ((int64_t)gz * n[1] + gy) * n[0] + gx;
+        const R r = Uin[c];
+        const R inv_rho = (R)1 / (DEV ? (R)1 + r : r);
+        sp[0][q] = r;
+        sp[1][q] = Uin[N + c] * inv_rho;
+        sp[2][q] = Uin[2 * N + c] * inv_rho;
+        sp[3][q] = Uin[3 * N + c] * inv_rho;
+        sp[4][q] = Uin[4 * N + c] * inv_rho;
+    }
+    __syncthreads();
+
+    // Phase 2: gradients.
+    for (int q = tid; q < TL::NG; q += nthr) {
+        const int lx = q % TL::GX, ly = (q / TL::GX) % TL::GY, lz = q / (TL::GX * TL::GY);
+        int g[3];
+        bool in[3];
+        g[0] = gcell(i0 - 1 + lx, 0, in[0]);
+        g[1] = gcell(j0 - 1 + ly, 1, in[1]);
+        g[2] = gcell(k0 - 1 + lz, 2, in[2]);
+        if (!(in[0] && in[1] && in[2])) continue;
+        const int pc = TL::pidx(lx + 1, ly + 1, lz + 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int step = a == 0 ? 1 : (a == 1 ? TL::PX : TL::PX * TL::PY);
+            const R wP = (R)d.w[a][g[a]];
+            const bool wlo = !d.periodic[a] && g[a] == 0, whi = !d.periodic[a] && g[a] == n[a] - 1;
+            const R wl = wlo ? (R)0 : (R)d.w[a][d.periodic[a] ? wrap(g[a] - 1, n[a]) : g[a] - 1];
+            const R wh = whi ? (R)0 : (R)d.w[a][d.periodic[a] ? wrap(g[a] + 1, n[a]) : g[a] + 1];
+#pragma unroll
+            for (int p = 0; p < NPRIM; ++p) {
+                const R vP = sp[p][pc];
+                auto wallv = [&](int side) -> R {
+                    if (p == 0) return vP;
+                    if (p < 4) return (R)0;
+                    return d.kind[side] == kIsothermal ? (R)d.Tw[side] : vP;
+                };
+                const R flo = wlo ? wallv(2 * a) : (vP * wl + sp[p][pc - step] * wP) / (wP + wl);
+                const R fhi = whi ? wallv(2 * a + 1) : (vP * wh + sp[p][pc + step] * wP) / (wP + wh);
+                sg[p][a][q] = (fhi - flo) / wP;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase 3: faces of the three axes.
+    for (int q = tid; q < TL::NF0 + TL::NF1 + TL::NF2; q += nthr) {
+        int ax, f[3], qq = q;
+        if (qq < TL::NF0) {
+            ax = 0;
+            f[0] = qq % (TX + 1);
+            f[1] = (qq / (TX + 1)) % TY;
+            f[2] = qq / ((TX + 1) * TY);
+        } else if ((qq -= TL::NF0) < TL::NF1) {
+            ax = 1;
+            f[0] = qq % TX;
+            f[1] = (qq / TX) % (TY + 1);
+            f[2] = qq / (TX * (TY + 1));
+        } else {
+            qq -= TL::NF1;
+            ax = 2;
+            f[0] = qq % TX;
+            f[1] = (qq / TX) % TY;
+            f[2] = qq / (TX * TY);
+        }
+        bool skip = false;
+        for (int a = 0; a < 3; ++a) {
+            const int gcoord = org[a] + f[a];
+            if (a == ax ? gcoord > n[a] : gcoord >= n[a]) skip = true;
+        }
+        if (skip) continue;
+        // local frame: normal ax, then the other axes in increasing order
+        const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+        const int ax_loc[3] = {ax, t1, t2};
+        const int gf = org[ax] + f[ax];
+        R area = (R)1;
+        for (int a = 0; a < 3; ++a)
+            if (a != ax) area *= (R)d.w[a][org[a] + f[a]];
+        R F[5];
+        const int cR[3] = {f[0], f[1], f[2]};
+        int cL[3] = {f[0], f[1], f[2]};
+        cL[ax] -= 1;
+        if (!d.periodic[ax] && (gf == 0 || gf == n[ax])) {
+            const int side = 2 * ax + (gf == 0 ? 0 : 1);
+            const int *cw = gf == 0 ? cR : cL;
+            const int pc = TL::pidx(cw[0] + 2, cw[1] + 2, cw[2] + 2);
+            const R sgn = gf == 0 ? (R)-1 : (R)1;
+            const R rP = sp[0][pc];
+            const R rho = DEV ? (R)1 + rP : rP;
+            const R d_w = (R)0.5 * (R)d.w[ax][gf == 0 ? 0 : n[ax] - 1];
+            const R mloc[3] = {rho * sp[1 + ax_loc[0]][pc], rho * sp[1 + ax_loc[1]][pc], rho * sp[1 + ax_loc[2]][pc]};
+            R G[5];
+            wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, d.kind[side] == kIsothermal, (R)d.Tw[side],
+                                 ph, G);
+            F[0] = G[0];
+            F[4] = G[4];
+            for (int k = 0; k < 3; ++k) F[1 + ax_loc[k]] = G[1 + k];
+        } else {
+            Side<R, 3> A, B;
+            const int pL = TL::pidx(cL[0] + 2, cL[1] + 2, cL[2] + 2), pR = TL::pidx(cR[0] + 2, cR[1] + 2, cR[2] + 2);
+            const int gL = TL::gidx(cL[0] + 1, cL[1] + 1, cL[2] + 1), gR = TL::gidx(cR[0] + 1, cR[1] + 1, cR[2] + 1);
+            // local primitive order: r, u_n, u_t1, u_t2, T
+            const int pmap[5] = {0, 1 + ax_loc[0], 1 + ax_loc[1], 1 + ax_loc[2], 4};
+#pragma unroll
+            for (int p = 0; p < 5; ++p) {
+                A.v[p] = sp[pmap[p]][pL];
+                B.v[p] = sp[pmap[p]][pR];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    A.g[k][p] = sg[pmap[p]][ax_loc[k]][gL];
+                    B.g[k][p] = sg[pmap[p]][ax_loc[k]][gR];
+                }
+            }
+            const int gl = org[ax] + cL[ax], gr = gf;
+            const R dL = (R)0.5 * (R)d.w[ax][d.periodic[ax] ? wrap(gl, n[ax]) : gl];
+            const R dR = (R)0.5 * (R)d.w[ax][d.periodic[ax] ? wrap(gr, n[ax]) : gr];
+            R fdir[3];
+            for (int k = 0; k < 3; ++k) fdir[k] = (d.force_pred && d.gaxis == ax_loc[k]) ? (R)1 : (R)0;
+            R G[5];
+            face_flux<R, 3, DEV>(A, B, dL, dR, fdir, ph, G);
+            F[0] = G[0];
+            F[4] = G[4];
+            for (int k = 0; k < 3; ++k) F[1 + ax_loc[k]] = G[1 + k];
+        }
+        if (ax == 0) {
+            const int o = (f[2] * TY + f[1]) * (TX + 1) + f[0];
+            for (int k = 0; k < 5; ++k) sf0[k][o] = F[k] * area;
+        } else if (ax == 1) {
+            const int o = (f[2] * (TY + 1) + f[1]) * TX + f[0];
+            for (int k = 0; k < 5; ++k) sf1[k][o] = F[k] * area;
+        } else {
+            const int o = (f[2] * TY + f[1]) * TX + f[0];
+            for (int k = 0; k < 5; ++k) sf2[k][o] = F[k] * area;
+        }
+    }
+    __syncthreads();
+
+    // Phase 4: update.
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const R dtR = (R)d.dt;
+    for (int q = tid; q < TX * TY * TZ; q += nthr) {
+        const int x = q % TX, y = (q / TX) % TY, z = q / (TX * TY);
+        const int gx = i0 + x, gy = j0 + y, gz = k0 + z;
+        if (gx >= n[0] || gy >= n[1] || gz >= n[2]) continue;
+        const int64_t c = ((int64_t)gz * n[1] + gy) * n[0] + gx;
+        const R dt_dV = dtR / ((R)d.w[0][gx] * (R)d.w[1][gy] * (R)d.w[2][gz]);
+        const int o0 = (z * TY + y) * (TX + 1) + x;
+        const int o1 = (z * (TY + 1) + y) * TX + x;
+        const int o2 = (z * TY + y) * TX + x;
+        R Un[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const R div = (sf0[k][o0] - sf0[k][o0 + 1]) + (sf1[k][o1] - sf1[k][o1 + TX]) +
+                          (sf2[k][o2] - sf2[k][o2 + TX * TY]);
+            Un[k] = Uin[k * N + c] + dt_dV * div;
+        }
+        const int pc = TL::pidx(x + 2, y + 2, z + 2);
+        const R rP = sp[0][pc];
+        const R rhoP = DEV ? (R)1 + rP : rP;
+        const R TP = sp[4][pc];
+        if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Uout[k * N + c] = Un[k];
+        if (RES) {
+            const double rn = (double)Un[0];
+            const double rhon = DEV ? 1.0 + rn : rn;
+            double an = 0.0, ao = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double un = (double)Un[1 + a] / rhon, uo = (double)sp[1 + a][pc];
+                an += un * un;
+                ao += uo * uo;
+            }
+            const double Tn = (double)Un[4] / rhon + (DEV ? kT0 : 0.0);
+            const double To = (double)TP + (DEV ? kT0 : 0.0);
+            const bool ok = (an < 0.25 * kCs2) && (Tn == Tn) && (fabs(Tn) < 1e30);
+            an = sqrt(an);
+            ao = sqrt(ao);
+            acc[0] += fabs(an - ao);
+            acc[1] += an;
+            acc[2] += fabs(Tn - To);
+            acc[3] += Tn;
+            acc[4] += ok ? 0.0 : 1.0;
+        }
+    }
+    if (RES) {
+        block_sums<kPartials>(acc, sred);
+        if (tid == 0)
+            for (int k = 0; k < kPartials; ++k) part[k] = acc[k];
+    }
+}
+
+}  // namespace rtlbfs

@@ -1,0 +1,143 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol the header declares, and its host-only entry points and
+argument validation behave as documented."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2202_13449_amd as rt
+from paper_2202_13449_amd import rtlbfs as rtb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "rtlbfs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtlbfs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rt.load_library()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror_covers_all_codes():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert rt.strerror(code) and rt.strerror(code) != "unknown status"
+    assert rt.strerror(-99) == "unknown status"
+
+
+def test_opts_defaults():
+    o = rt.make_opts()
+    assert o.precision == rt.FP64_PLAIN and o.residual_every == 100 and o.mass_fix_every == 1000
+    assert o.graph_steps == 0 and o.phys_given == 0 and o.dtl == 0.0 and o.dt == 0.0
+
+
+def test_mesh_nodes_match_oracle_mesh():
+    """The library's Eq. 74 mesh equals the oracle's (both from the equation)."""
+    from oracle import mesh_nodes as orc_mesh
+    for n, phi in [(64, 0.0), (256, 1.5), (192, 1.8), (7, 2.0)]:
+        x, L = rt.mesh_nodes(n, phi)
+        y, M = orc_mesh(n, phi)
+        assert abs(L - M) <= 1e-12 * M
+        assert np.abs(x - y).max() <= 1e-12 * M
+
+
+def test_workspace_bytes():
+    lib = rt.load_library()
+    m = rt.make_mesh(2, (64, 64))
+    o = rt.make_opts()
+    b64 = lib.rtlbfs_workspace_bytes(C.byref(m), C.byref(o))
+    o32 = rt.make_opts(precision=rt.FP32_DEV)
+    b32 = lib.rtlbfs_workspace_bytes(C.byref(m), C.byref(o32))
+    assert b64 >= 2 * 4 * 4096 * 8 and b32 >= 2 * 4 * 4096 * 4 and b64 > b32
+    assert b64 % 256 == 0
+    bad = rt.make_mesh(2, (3, 64))
+    assert lib.rtlbfs_workspace_bytes(C.byref(bad), C.byref(o)) == 0
+    assert lib.rtlbfs_workspace_bytes(None, C.byref(o)) == 0
+
+
+def _create(mesh, bc, Ra=1e3, Pr=0.71, Ma=0.1, opts=None):
+    lib = rt.load_library()
+    h = C.c_void_p()
+    o = opts or rt.make_opts()
+    rc = lib.rtlbfs_create(C.byref(mesh), Ra, Pr, Ma, C.byref(bc), C.byref(o), None, None, 0, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["dim", "small", "periodic_pair", "periodic_stretch", "Ra", "Pr", "Ma", "gravity",
+                                  "precision", "kind"])
+def test_create_rejects_invalid_problems_before_touching_the_device(case):
+    mesh = rt.make_mesh(2, (16, 16))
+    bc = rt.make_bc((1, 1, 2, 2), (0.5, -0.5, 0, 0), 1)
+    Ra, Pr, Ma, opts = 1e3, 0.71, 0.1, None
+    if case == "dim":
+        mesh.dim = 4
+    elif case == "small":
+        mesh.n[0] = 3
+    elif case == "periodic_pair":
+        bc.kind[0] = rt.PERIODIC
+    elif case == "periodic_stretch":
+        bc.kind[0] = bc.kind[1] = rt.PERIODIC
+        mesh.stretch[0] = 1.5
+    elif case == "Ra":
+        Ra = -1.0
+    elif case == "Pr":
+        Pr = 0.0
+    elif case == "Ma":
+        Ma = 0.5
+    elif case == "gravity":
+        bc.gravity_axis = 2
+    elif case == "precision":
+        opts = rt.make_opts(precision=7)
+    elif case == "kind":
+        bc.kind[2] = 9
+    rc, h = _create(mesh, bc, Ra, Pr, Ma, opts)
+    assert rc == rt.EINVAL and not h.value
+
+
+def test_null_arguments():
+    lib = rt.load_library()
+    assert lib.rtlbfs_step(None, 1) == rt.EINVAL
+    assert lib.rtlbfs_destroy(None) == rt.OK
+    assert lib.rtlbfs_opts_init(None) == rt.EINVAL
+    assert lib.rtlbfs_mesh_nodes(0, 0.0, None, None) == rt.EINVAL
+    assert lib.rtlbfs_last_error(None) == b""
+    mesh = rt.make_mesh(2, (16, 16))
+    bc = rt.make_bc((1, 1, 2, 2), (0.5, -0.5, 0, 0), 1)
+    o = rt.make_opts()
+    assert lib.rtlbfs_create(C.byref(mesh), 1e3, 0.71, 0.1, C.byref(bc), C.byref(o), None, None, 0, None) \
+        == rt.EINVAL
+
+
+def test_binding_refuses_to_run_without_a_gpu(monkeypatch):
+    """The product path has no CPU fallback: without a GPU it raises."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError, match="needs a HIP GPU"):
+        rt.Solver(2, (16, 16), (0, 0), (1, 1, 2, 2), (0.5, -0.5, 0, 0), 1)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(rtb, "_lib", None)
+    monkeypatch.setattr(rtb, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError, match="missing"):
+        rtb.load_library()
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2202_13449_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "rtlbfs_oracle" not in text and "orc_" not in text, f

@@ -1,0 +1,245 @@
+"""GPU parity: the HIP kernels (through the C ABI) against the FP64 oracle.
+
+Element-by-element comparison of the absolute primitive fields on the same
+seeded inputs.  Tolerance for the FP64 paths: max |gpu - oracle| / scale <=
+1e-12 per field, where the scale is max |oracle| for rho and T and
+max(max |u|, V_c) for the velocity components (V_c = Ma, the characteristic
+velocity of Eq. 63).  The kernels contract multiply-adds and sum fluxes in a
+different order; in plain storage the rounding of rho ~ 1 (1e-16) enters the
+pressure gradient every step, so early in a run, when |u| << V_c, the velocity
+differences measured against max |u| alone would reflect that rounding, not
+the scheme.  The FP32 deviation path is compared
+against the oracle's FP64 deviation form with a tolerance derived from FP32
+rounding, and on Nusselt numbers at steady state (1e-4 relative).
+"""
+import numpy as np
+import pytest
+
+import inputs
+import paper_2202_13449_amd as rt
+from oracle import INIT_CONDUCTION, INIT_REST, Oracle, OracleConfig, physics_from_ra, mesh_nodes
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+def make_pair(dim, n, stretch, kind, Tdev, gaxis, Ra=1e4, Pr=0.71, Ma=0.1, precision=rt.FP64_PLAIN, seed=1,
+              noise=1e-3, init=INIT_REST, dtl=1.0, dt=0.0, residual_every=100, graph_steps=0, L_axis=None):
+    """A GPU solver and an oracle run of the same problem (the oracle is given
+    the parameters the library derived, read back through rtlbfs_get_info)."""
+    s = rt.Solver(dim, n, stretch, kind, Tdev, gaxis, Ra=Ra, Pr=Pr, Ma=Ma, precision=precision, seed=seed,
+                  noise_amp=noise, init=init, dtl=dtl, dt=dt, residual_every=residual_every,
+                  graph_steps=graph_steps)
+    info = s.info
+    # independent derivation of Eq. 63 on the oracle side
+    La = info.L
+    nu, chi, bg = physics_from_ra(Ra, Pr, Ma, La)
+    assert abs(nu - info.nu) <= 1e-14 * nu and abs(chi - info.chi) <= 1e-14 * chi
+    assert abs(bg - info.beta_g) <= 1e-14 * bg
+    cfg = OracleConfig(dim=dim, n=tuple(n) + (1,) * (3 - len(n)), stretch=tuple(stretch) + (0.0,) * (3 - len(stretch)),
+                       bc=tuple(kind) + (0,) * (6 - len(kind)), Tw=tuple(Tdev) + (0.0,) * (6 - len(Tdev)),
+                       gravity_axis=gaxis, nu=nu, chi=chi, beta_g=bg, dtl=info.dtl, dt=info.dt,
+                       deviation=0 if precision == rt.FP64_PLAIN else 1, init=init, seed=seed, noise_amp=noise)
+    return s, Oracle(cfg)
+
+
+def field_rel(s, o, dim, Vc=0.1):
+    out = []
+    for f in range(dim + 2):
+        a, b = s.field(f), o.prim(f)
+        scale = max(np.abs(b).max(), Vc if 1 <= f <= dim else 0.0, 1e-300)
+        out.append(float(np.abs(a - b).max() / scale))
+    return out
+
+
+DHC2 = dict(kind=(1, 1, 2, 2), Tdev=(0.5, -0.5, 0.0, 0.0), gaxis=1)
+
+
+def test_initial_state_is_identical():
+    """Both sides implement SplitMix64 and the conduction profile from their
+    definitions: the uploaded initial state matches the oracle's bit for bit."""
+    for prec in (rt.FP64_PLAIN, rt.FP64_DEV):
+        s, o = make_pair(2, (40, 24), (1.5, 1.5), **DHC2, precision=prec, init=INIT_CONDUCTION, noise=1e-3, seed=9)
+        for f in range(4):
+            assert np.array_equal(s.stored(f), o.stored(f)), (prec, f)
+
+
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP64_DEV])
+@pytest.mark.parametrize("shape,stretch", [((64, 64), (0.0, 0.0)), ((70, 45), (1.5, 1.5)), ((33, 9), (0.0, 0.0))])
+def test_fp64_cavity_parity(prec, shape, stretch):
+    """Differentially heated cavity, several tiles with ragged tails,
+    uniform and stretched: fields after 600 steps within 1e-12."""
+    s, o = make_pair(2, shape, stretch, **DHC2, Ra=1e5, precision=prec, noise=1e-3)
+    s.step(600)
+    o.step(600)
+    rel = field_rel(s, o, 2)
+    assert max(rel) <= FP64_TOL, rel
+
+
+def test_fp64_c1_parity_1000_steps_and_diagnostics():
+    """64^2 uniform cavity at Ra = 1e3 (the small configuration): fields,
+    Eq. 65 residual, Nusselt numbers and mass after 1000 steps."""
+    s, o = make_pair(2, (64, 64), (0.0, 0.0), **DHC2, Ra=1e3, noise=1e-6)
+    s.step(1000)
+    o.step(1000)
+    assert max(field_rel(s, o, 2)) <= FP64_TOL
+    ru, rT = s.residual()
+    ou, oT = o.residual()
+    assert abs(ru - ou) <= 1e-9 * ou and abs(rT - oT) <= 1e-9 * oT
+    a, b = s.nusselt(), o.nusselt()
+    for k in a:
+        assert abs(a[k] - b[k]) <= 1e-11 * abs(b[k]), (k, a[k], b[k])
+    ig, io = s.integrals(), o.integrals()
+    assert abs(ig["volume"] - io["volume"]) <= 1e-12 * io["volume"]
+    assert abs(ig["mass_dev"] - io["mass_dev"]) <= 1e-12 * io["volume"]
+
+
+def test_fp64_periodic_rayleigh_benard_parity():
+    """Rayleigh-Benard box periodic in x (wrapped halos, ragged periodic
+    tiles): 400 steps."""
+    bc, Tw, g = inputs.rb_bc()
+    s, o = make_pair(2, (72, 20), (0.0, 0.0), bc[:4], Tw[:4], g, Ra=1e6, init=INIT_CONDUCTION, noise=1e-3, seed=3)
+    s.step(400)
+    o.step(400)
+    rel = field_rel(s, o, 2)
+    assert max(rel) <= FP64_TOL, rel
+
+
+def test_fp64_fully_periodic_gaussian_hill_parity():
+    """Periodic box with given nu/chi, dtl = 0.5, Delta t = 1 (the Sec. 4.1
+    set-up) starting from the Gaussian hill."""
+    N = 40
+    L = N / 2.0
+    chi = 0.1
+    u0 = 10.0 * chi / L
+    s = rt.Solver(2, (N, N), (0, 0), (0, 0, 0, 0), (0, 0, 0, 0), -1, phys_given=1, nu=chi, chi=chi, beta_g=0.0,
+                  dtl=0.5, dt=1.0)
+    o = Oracle(OracleConfig(n=(N, N), bc=(0,) * 6, gravity_axis=-1, nu=chi, chi=chi, dtl=0.5, dt=1.0))
+    xc, _ = o.axis(0)
+    yc, _ = o.axis(1)
+    u = np.zeros((2, N * N))
+    u[0] = u0
+    T = inputs.gaussian_hill(xc, yc, L, 0.0, chi, u0).reshape(-1)
+    s.set_state(np.ones(N * N), u, T)
+    o.set_prim(np.ones(N * N), u, T)
+    s.step(80)
+    o.step(80)
+    assert max(field_rel(s, o, 2)[1:]) <= FP64_TOL  # rho stays exactly 1 on both
+
+
+def test_fp64_random_state_parity_all_boundary_kinds():
+    """Random smooth-ish state, mixed walls (isothermal, adiabatic) and
+    gravity along x: 200 steps."""
+    s, o = make_pair(2, (37, 29), (1.2, 0.0), (1, 2, 2, 1), (0.3, 0.0, 0.0, -0.2), 0, Ra=1e5)
+    rho, u, T = inputs.random_state(37 * 29, 2, seed=11)
+    s.set_state(rho, u, T)
+    o.set_prim(rho, u, T)
+    s.step(200)
+    o.step(200)
+    assert max(field_rel(s, o, 2)) <= FP64_TOL
+
+
+def test_graph_replay_equals_direct_launches():
+    """Chunks replayed from captured HIP graphs give exactly the same state as
+    kernels launched one by one, over several replays with host work in
+    between."""
+    args = (2, (48, 40), (0, 0), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"])
+    a = rt.Solver(*args, Ra=1e5, noise_amp=1e-3, seed=2, residual_every=25, graph_steps=0)
+    b = rt.Solver(*args, Ra=1e5, noise_amp=1e-3, seed=2, residual_every=25, graph_steps=-1)
+    for _ in range(4):
+        a.step(50)
+        b.step(50)
+        assert a.residual() == b.residual()
+        for f in range(4):
+            assert np.array_equal(a.stored(f), b.stored(f))
+    a.step(37)  # partial chunk + parity flip
+    b.step(37)
+    for f in range(4):
+        assert np.array_equal(a.stored(f), b.stored(f))
+
+
+def test_rest_state_bitwise_and_mass_conservation_on_gpu():
+    s = rt.Solver(2, (40, 30), (1.5, 1.5), (2, 1, 2, 1), (0, 0, 0, 0), 1, Ra=1e5)
+    before = [s.stored(f) for f in range(4)]
+    s.step(300)
+    for f in range(4):
+        assert np.array_equal(s.stored(f), before[f])
+    s, o = make_pair(2, (40, 30), (1.5, 1.5), **DHC2, Ra=1e6, noise=1e-2)
+    m0 = s.integrals()["mass_dev"]
+    s.step(2000)
+    vol = s.integrals()["volume"]
+    assert abs(s.integrals()["mass_dev"] - m0) <= 1e-13 * vol
+
+
+def test_minimum_mesh_and_single_tile():
+    s, o = make_pair(2, (4, 4), (0, 0), **DHC2, Ra=1e4)
+    s.step(50)
+    o.step(50)
+    assert max(field_rel(s, o, 2)) <= FP64_TOL
+
+
+def test_c2_full_size_prefix_fp64():
+    """256^2 tanh (phi = 1.5) cavity at Ra = 1e6, the benchmarked
+    configuration, in the benchmarked launch configuration: 100 steps
+    compared cell by cell with the oracle."""
+    s, o = make_pair(2, (256, 256), (1.5, 1.5), **DHC2, Ra=1e6, noise=1e-6)
+    s.step(100)
+    o.step(100)
+    rel = field_rel(s, o, 2)
+    assert max(rel) <= FP64_TOL, rel
+
+
+# ------------------------------------------------------------- 3D --------
+
+DHC3 = dict(kind=(1, 1, 2, 2, 2, 2), Tdev=(-0.5, 0.5, 0, 0, 0, 0), gaxis=2)
+
+
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP64_DEV])
+def test_fp64_3d_cavity_parity(prec):
+    """3D cubic cavity (cold x = 0, hot x = L, gravity +z), stretched mesh,
+    ragged tiles in every direction: 120 steps."""
+    s, o = make_pair(3, (19, 13, 10), (1.8, 1.8, 1.8), **DHC3, Ra=1e5, precision=prec, noise=1e-3)
+    s.step(120)
+    o.step(120)
+    rel = field_rel(s, o, 3)
+    assert max(rel) <= FP64_TOL, rel
+
+
+def test_fp64_3d_periodic_and_diagnostics():
+    s, o = make_pair(3, (12, 10, 9), (0, 0, 0), (0, 0, 1, 1, 2, 2), (0, 0, 0.5, -0.5, 0, 0), 1, Ra=5e4,
+                     init=INIT_CONDUCTION, noise=1e-2)
+    s.step(100)
+    o.step(100)
+    rel = field_rel(s, o, 3)
+    assert max(rel) <= FP64_TOL, rel
+    a, b = s.nusselt(), o.nusselt()
+    for k in a:
+        assert abs(a[k] - b[k]) <= 1e-11 * abs(b[k]), k
+
+
+# ------------------------------------------------------------- FP32 ------
+
+def test_fp32_deviation_short_horizon_fields():
+    """FP32 deviation storage against the oracle's FP64 deviation form:
+    200 steps of a developing Ra = 1e5 cavity; the deviation variables keep
+    the FP32 rounding at ~1e-7 of the field scale."""
+    s, o = make_pair(2, (48, 48), (1.5, 1.5), **DHC2, Ra=1e5, precision=rt.FP32_DEV, noise=1e-3)
+    s.step(200)
+    o.step(200)
+    rel = field_rel(s, o, 2)
+    # rho ~ 1: compare the deviation r instead
+    r_gpu, r_orc = s.stored(0), o.stored(0)
+    assert np.abs(r_gpu - r_orc).max() <= 1e-5 * np.abs(r_orc).max()
+    assert max(rel[1:]) <= 1e-4, rel
+
+
+def test_fp32_deviation_nusselt_at_steady_state():
+    """At steady state (Ra = 1e3, 32^2) the FP32 deviation path reproduces the
+    FP64 oracle's Nusselt numbers within 1e-4 relative."""
+    s, o = make_pair(2, (32, 32), (0, 0), **DHC2, Ra=1e3, precision=rt.FP32_DEV, noise=1e-6)
+    o.step(12000)
+    s.step(12000)
+    a, b = s.nusselt(), o.nusselt()
+    for k in ("hot_avg", "cold_avg", "volume", "hot_max", "cold_max"):
+        assert abs(a[k] - b[k]) <= 1e-4 * abs(b[k]), (k, a[k], b[k])
