@@ -1,0 +1,151 @@
+"""Throughput of the RTLBFS time step on one MI355X.
+
+Workload: 2D differentially heated cavity, 256 x 256 tanh-stretched mesh
+(phi = 1.5 on both axes, finest cell = 1), Ra = 1e6, Pr = 0.71, V_c = 0.1,
+hot / cold isothermal side walls, adiabatic top / bottom, fluid at rest with
+seeded 1e-6 temperature noise.  One step is one full RTLBFS time step (face
+lattice predictor, fluxes, divergence, update) with its FP64 reductions at
+their cadence (Eq. 65 residual every 100 steps, mass-drift correction every
+1000 steps), replayed from captured HIP graphs.  `value` is the FP32
+deviation-storage path; the FP64 plain path is timed beside it on the same
+workload.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_CELLS_SIDE = 256
+STRETCH = 1.5
+RA, PR, MA = 1e6, 0.71, 0.1
+KIND = (1, 1, 2, 2)           # isothermal x walls, adiabatic y walls
+TDEV = (0.5, -0.5, 0.0, 0.0)  # hot at x = 0
+GAXIS = 1
+BYTES_PER_CELL = {"f32": 4 * 4 * 2, "f64": 4 * 8 * 2}  # read + write of the 4 stored fields
+HBM_PEAK_GBS = 8000.0
+
+
+def make_solver(rt, precision):
+    return rt.Solver(2, (N_CELLS_SIDE, N_CELLS_SIDE), (STRETCH, STRETCH), KIND, TDEV, GAXIS, Ra=RA, Pr=PR, Ma=MA,
+                     precision=precision, seed=1, noise_amp=1e-6, residual_every=100, mass_fix_every=1000)
+
+
+def time_path(rt, torch, precision, steps, warmup):
+    s = make_solver(rt, precision)
+    s.step(warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.sync()  # raises on divergence
+    ms = e0.elapsed_time(e1)
+    nu = s.nusselt()
+    res = s.residual()
+    return dict(solver=s, event_ms=ms, wall_s=wall, nu=nu, res=res)
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle, as written, on a bounded sample of the same workload."""
+    from oracle import Oracle, OracleConfig, physics_from_ra, mesh_nodes
+
+    _, L = mesh_nodes(N_CELLS_SIDE, STRETCH)
+    nu, chi, bg = physics_from_ra(RA, PR, MA, L)
+    o = Oracle(OracleConfig(n=(N_CELLS_SIDE, N_CELLS_SIDE), stretch=(STRETCH, STRETCH), bc=KIND + (0, 0),
+                            Tw=TDEV + (0, 0), gravity_axis=GAXIS, nu=nu, chi=chi, beta_g=bg, dtl=1.0,
+                            dt=min(0.5, 0.15 / max(nu, chi)), seed=1, noise_amp=1e-6))
+    t0 = time.perf_counter()
+    o.step(2)
+    per_step = (time.perf_counter() - t0) / 2
+    steps = max(5, int(seconds_target / per_step))
+    t0 = time.perf_counter()
+    o.step(steps)
+    el = time.perf_counter() - t0
+    cells = N_CELLS_SIDE * N_CELLS_SIDE
+    return {"value": cells * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the 256x256 tanh cavity (Ra=1e6), plain FP64 C oracle, one thread, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the RTLBFS step of one domain runs on a single MI355X; "
+              "multi-GPU sharding is not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2202_13449_amd as rt
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
+        return
+    cells = N_CELLS_SIDE * N_CELLS_SIDE
+    r32 = time_path(rt, torch, rt.FP32_DEV, args.steps, args.warmup)
+    ms32 = r32["event_ms"] / args.steps
+    value = cells / (ms32 * 1e-3)
+    out = {
+        "metric": "cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D differentially heated cavity 256x256 tanh (phi=1.5) Ra=1e6 Pr=0.71 "
+                               "FP32 deviation storage, FP64 reductions",
+                   "cells": cells, "residual_every": 100, "mass_fix_every": 1000},
+    }
+    bpl = BYTES_PER_CELL["f32"] * cells  # algorithmic bytes per step-kernel launch
+    achieved = bpl / (ms32 * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    out["nu_fp32"] = r32["nu"]
+    if not args.fp32_only:
+        r64 = time_path(rt, torch, rt.FP64_PLAIN, args.steps, args.warmup)
+        ms64 = r64["event_ms"] / args.steps
+        out["fp64_plain"] = {"value": cells / (ms64 * 1e-3), "ms_per_step": ms64,
+                             "hbm_gbs": BYTES_PER_CELL["f64"] * cells / (ms64 * 1e-3) / 1e9,
+                             "nu": r64["nu"]}
+        out["nu_rel_diff_fp32_vs_fp64"] = {k: abs(r32["nu"][k] - r64["nu"][k]) / abs(r64["nu"][k])
+                                           for k in r64["nu"]}
+        out["speedup_fp32_vs_fp64"] = ms64 / ms32
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
