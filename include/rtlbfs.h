@@ -103,7 +103,8 @@ typedef struct {
     int buoyancy_update_only; /* 1: force only in the cell update (not in m*) */
     int phys_given;       /* 1: use nu, chi, beta_g below and ignore Ra, Pr, Ma */
     double nu, chi, beta_g;
-    int tile;             /* kernel tile selector; 0 -> automatic */
+    int tile;             /* 2D kernel tile: 0 -> autotuned at create (every shape timed on the
+                             live state); 1..5 -> 32x8, 16x16, 64x4, 16x8, 8x8 cells */
 } rtlbfs_opts;
 
 typedef struct {
@@ -122,6 +123,7 @@ typedef struct {
     double length[3];           /* domain length per axis */
     int precision;
     int tile_x, tile_y, tile_z; /* tile the step kernel runs with */
+    double tune_ms[8];          /* autotuner: ms per step of each 2D tile shape (0 if not timed) */
 } rtlbfs_info;
 
 typedef struct rtlbfs_handle *rtlbfs_t;

@@ -22,11 +22,12 @@ using namespace rtlbfs;
 // ----------------------------------------------------------------- kernels --
 
 template <typename R, bool DEV, int TX, int TY, bool RES>
-__global__ void __launch_bounds__(256) k_step2d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
-                                                double *__restrict__ parts) {
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
-    tile_step_2d<R, DEV, TX, TY, RES>(d, i0, j0, Uin, Uout,
-                                      parts + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * kPartials);
+__global__ void __launch_bounds__((tile2_threads<TX, TY>())) k_step2d(Domain d, const R *__restrict__ Uin,
+                                                                    R *__restrict__ Uout, double *__restrict__ parts) {
+    const int ntx = (d.n[0] + TX - 1) / TX;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int i0 = (t % ntx) * TX, j0 = (t / ntx) * TY;
+    tile_step_2d<R, DEV, TX, TY, RES>(d, i0, j0, Uin, Uout, parts + (int64_t)t * kPartials);
 }
 
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
@@ -40,7 +41,13 @@ __global__ void __launch_bounds__(TX * TY * TZ) k_step3d(Domain d, const R *__re
 
 namespace {
 
-constexpr int kTX2 = 32, kTY2 = 8;             // 2D tile
+// 2D tile shapes the autotuner chooses from (opts.tile = index + 1).
+struct Tile2 {
+    int tx, ty;
+};
+constexpr Tile2 kTiles2[] = {{32, 8}, {16, 16}, {64, 4}, {16, 8}, {8, 8}};
+constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
+constexpr int kTX2 = 32, kTY2 = 8;             // largest 2D tile (sizes the partials buffer)
 constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per cell)
 constexpr int kRedBlocks = 512;                // blocks of the diagnostics kernels
 
@@ -82,8 +89,11 @@ struct Layout {
 
 int elem_size(int precision) { return precision == RTLBFS_FP32_DEV ? 4 : 8; }
 
-int step_blocks(const rtlbfs_mesh &m) {
-    if (m.dim == 2) return ((m.n[0] + kTX2 - 1) / kTX2) * ((m.n[1] + kTY2 - 1) / kTY2);
+int step_blocks(const rtlbfs_mesh &m, int tile = 0) {
+    if (m.dim == 2) {
+        const Tile2 t = kTiles2[tile];
+        return ((m.n[0] + t.tx - 1) / t.tx) * ((m.n[1] + t.ty - 1) / t.ty);
+    }
     return ((m.n[0] + kTX3 - 1) / kTX3) * ((m.n[1] + kTY3 - 1) / kTY3) * ((m.n[2] + kTZ3 - 1) / kTZ3);
 }
 
@@ -103,7 +113,8 @@ Layout make_layout(const rtlbfs_mesh &m, int precision) {
     off += copy_bytes;
     l.off_w = off;
     off += align256(sizeof(double) * (m.n[0] + m.n[1] + (m.dim == 3 ? m.n[2] : 0)));
-    l.nparts = std::max(step_blocks(m), kRedBlocks);
+    l.nparts = kRedBlocks;
+    for (int t = 0; t < (m.dim == 2 ? kNumTiles2 : 1); ++t) l.nparts = std::max(l.nparts, step_blocks(m, t));
     l.off_parts = off;
     off += align256(sizeof(double) * (size_t)l.nparts * 8);
     l.off_red = off;  // residual sums (8), Nusselt (8), integrals (4), M0 (1), mass-fix sums (4)
@@ -125,6 +136,8 @@ struct rtlbfs_handle {
     char *ws = nullptr;
     bool own_ws = false;
     int cur = 0;  // which ping-pong copy holds the state
+    int tile = 0; // index into kTiles2 (2D)
+    float tune_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // autotuner timings per tile (ms per step)
     int64_t steps = 0;
     int64_t since_fix = 0;
     bool res_valid = false;
@@ -252,35 +265,51 @@ int read_stored(rtlbfs_t h, int k, std::vector<double> &out) {
     return RTLBFS_OK;
 }
 
-template <typename R, bool DEV>
-hipError_t launch_step(rtlbfs_t h, bool res, hipStream_t s) {
-    const Domain &d = h->dom;
-    const R *Uin = (const R *)h->U(h->cur);
-    R *Uout = (R *)h->U(h->cur ^ 1);
-    if (d.dim == 2) {
-        dim3 grid((d.n[0] + kTX2 - 1) / kTX2, (d.n[1] + kTY2 - 1) / kTY2);
-        if (res) k_step2d<R, DEV, kTX2, kTY2, true><<<grid, 256, 0, s>>>(d, Uin, Uout, h->parts());
-        else k_step2d<R, DEV, kTX2, kTY2, false><<<grid, 256, 0, s>>>(d, Uin, Uout, h->parts());
-    } else {
-        dim3 grid((d.n[0] + kTX3 - 1) / kTX3, (d.n[1] + kTY3 - 1) / kTY3, (d.n[2] + kTZ3 - 1) / kTZ3);
-        constexpr int nt = kTX3 * kTY3 * kTZ3;
-        if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
-        else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
-    }
+template <typename R, bool DEV, int TX, int TY>
+hipError_t launch_step2d(const Domain &d, const R *Uin, R *Uout, double *parts, bool res, hipStream_t s) {
+    const int nb = ((d.n[0] + TX - 1) / TX) * ((d.n[1] + TY - 1) / TY);
+    constexpr int nt = tile2_threads<TX, TY>();
+    if (res) k_step2d<R, DEV, TX, TY, true><<<nb, nt, 0, s>>>(d, Uin, Uout, parts);
+    else k_step2d<R, DEV, TX, TY, false><<<nb, nt, 0, s>>>(d, Uin, Uout, parts);
     return hipGetLastError();
 }
 
-hipError_t enqueue_step(rtlbfs_t h, bool res, hipStream_t s) {
-    hipError_t e;
-    switch (h->opts.precision) {
-        case RTLBFS_FP64_PLAIN: e = launch_step<double, false>(h, res, s); break;
-        case RTLBFS_FP64_DEV: e = launch_step<double, true>(h, res, s); break;
-        default: e = launch_step<float, true>(h, res, s); break;
+template <typename R, bool DEV>
+hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
+    const Domain &d = h->dom;
+    const R *Uin = (const R *)h->U(src);
+    R *Uout = (R *)h->U(src ^ 1);
+    if (d.dim == 2) {
+        switch (tile) {
+            case 0: return launch_step2d<R, DEV, 32, 8>(d, Uin, Uout, h->parts(), res, s);
+            case 1: return launch_step2d<R, DEV, 16, 16>(d, Uin, Uout, h->parts(), res, s);
+            case 2: return launch_step2d<R, DEV, 64, 4>(d, Uin, Uout, h->parts(), res, s);
+            case 3: return launch_step2d<R, DEV, 16, 8>(d, Uin, Uout, h->parts(), res, s);
+            default: return launch_step2d<R, DEV, 8, 8>(d, Uin, Uout, h->parts(), res, s);
+        }
     }
+    dim3 grid((d.n[0] + kTX3 - 1) / kTX3, (d.n[1] + kTY3 - 1) / kTY3, (d.n[2] + kTZ3 - 1) / kTZ3);
+    constexpr int nt = kTX3 * kTY3 * kTZ3;
+    if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
+    else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
+    return hipGetLastError();
+}
+
+// One step kernel from copy `src` into the other copy (no state change on the host side).
+hipError_t launch_any(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
+    switch (h->opts.precision) {
+        case RTLBFS_FP64_PLAIN: return launch_step<double, false>(h, tile, src, res, s);
+        case RTLBFS_FP64_DEV: return launch_step<double, true>(h, tile, src, res, s);
+        default: return launch_step<float, true>(h, tile, src, res, s);
+    }
+}
+
+hipError_t enqueue_step(rtlbfs_t h, bool res, hipStream_t s) {
+    hipError_t e = launch_any(h, h->tile, h->cur, res, s);
     if (e != hipSuccess) return e;
     h->cur ^= 1;
     if (res) {
-        k_finalize_sum<kPartials><<<1, 256, 0, s>>>(h->parts(), step_blocks(h->mesh), h->res_out());
+        k_finalize_sum<kPartials><<<1, 256, 0, s>>>(h->parts(), step_blocks(h->mesh, h->tile), h->res_out());
         e = hipGetLastError();
     }
     return e;
@@ -310,6 +339,35 @@ hipError_t enqueue_mass_fix(rtlbfs_t h, hipStream_t s) {
     if (e != hipSuccess) return e;
     k_mass_fix<float><<<kRedBlocks, 256, 0, s>>>((float *)h->U(h->cur), h->lay.cells, h->fix_out(), h->m0());
     return hipGetLastError();
+}
+
+// Autotuner: time every 2D tile shape on the live state (each trial writes
+// only the spare copy, so the state is unchanged) and keep the fastest.
+int autotune_tile(rtlbfs_t h) {
+    if (h->mesh.dim != 2) return RTLBFS_OK;
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_t = 0;
+    for (int t = 0; t < kNumTiles2; ++t) {
+        for (int k = 0; k < 3; ++k) HIP_TRY(h, launch_any(h, t, h->cur, false, h->stream));
+        HIP_TRY(h, hipEventRecord(e0, h->stream));
+        for (int k = 0; k < 20; ++k) HIP_TRY(h, launch_any(h, t, h->cur, false, h->stream));
+        HIP_TRY(h, hipEventRecord(e1, h->stream));
+        HIP_TRY(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+        h->tune_ms[t] = ms / 20.0f;
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->tile = best_t;
+    return RTLBFS_OK;
 }
 
 // Capture `len` steps (the last with the residual) starting from copy `par`.
@@ -535,6 +593,21 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
             return r2;
         }
     }
+    // Kernel tile: fixed by opts.tile (1-based), or chosen by the autotuner.
+    if (D == 2 && o.tile > 0) {
+        if (o.tile > kNumTiles2) {
+            rtlbfs_destroy(h);
+            g_create_err = "opts.tile out of range";
+            return RTLBFS_EINVAL;
+        }
+        h->tile = o.tile - 1;
+    } else if (D == 2) {
+        rc = autotune_tile(h);
+        if (rc != RTLBFS_OK) {
+            rtlbfs_destroy(h);
+            return rc;
+        }
+    }
     *out = h;
     return RTLBFS_OK;
 }
@@ -698,9 +771,10 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
     out->dt = h->dom.dt;
     for (int a = 0; a < 3; ++a) out->length[a] = a < h->mesh.dim ? h->length[a] : 1.0;
     out->precision = h->opts.precision;
+    for (int t = 0; t < 8; ++t) out->tune_ms[t] = h->tune_ms[t];
     if (h->mesh.dim == 2) {
-        out->tile_x = kTX2;
-        out->tile_y = kTY2;
+        out->tile_x = kTiles2[h->tile].tx;
+        out->tile_y = kTiles2[h->tile].ty;
         out->tile_z = 1;
     } else {
         out->tile_x = kTX3;

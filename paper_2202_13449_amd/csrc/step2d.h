@@ -10,11 +10,30 @@
 //      fluxes go to LDS and are shared by the two cells of the face;
 //   4. divergence, Boussinesq source, forward-Euler update (Eqs. 57-59, 64),
 //      and on residual steps the FP64 partial sums of Eq. 65.
+// The block has one thread per face of the tile (rounded up to whole
+// wavefronts), so every phase is a single pass and each CU keeps several
+// wavefronts per SIMD in flight.
 #pragma once
 
 #include "rtlbfs_device.h"
 
 namespace rtlbfs {
+
+template <int TX, int TY>
+constexpr int tile2_threads() {
+    return (((TX + 1) * TY + TX * (TY + 1)) + 63) / 64 * 64;
+}
+
+// Block -> tile order that keeps each XCD on a contiguous band of tiles.
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8); giving XCD k the tiles [k*nb/8, (k+1)*nb/8) makes the halo of most
+// tiles, and the state written by the previous step, local to that XCD's L2.
+__device__ inline int xcd_tile(int b, int nb) {
+    constexpr int kXcd = 8;
+    const int full = nb / kXcd * kXcd;
+    if (b >= full) return b;
+    return (b % kXcd) * (full / kXcd) + b / kXcd;
+}
 
 template <typename R, bool DEV, int TX, int TY, bool RES>
 __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, const R *__restrict__ Uin,
@@ -25,6 +44,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     __shared__ R sg[4][2][GY][GX];
     __shared__ R sfx[4][TY][TX + 1];
     __shared__ R sfy[4][TY + 1][TX];
+    __shared__ R sc[4][TY][TX];  // old conserved state of the tile cells
     __shared__ double sred[kPartials * 16];
 
     const int nx = d.n[0], ny = d.n[1];
@@ -45,6 +65,13 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
         const int64_t c = (int64_t)gj * nx + gi;
         const R r = Uin[c], mx = Uin[N + c], my = Uin[2 * N + c], e = Uin[3 * N + c];
         const R inv_rho = (R)1 / (DEV ? (R)1 + r : r);
+        const int ti = li - 2, tj = lj - 2;
+        if (ti >= 0 && ti < TX && tj >= 0 && tj < TY) {
+            sc[0][tj][ti] = r;
+            sc[1][tj][ti] = mx;
+            sc[2][tj][ti] = my;
+            sc[3][tj][ti] = e;
+        }
         sp[0][lj][li] = r;
         sp[1][lj][li] = mx * inv_rho;
         sp[2][lj][li] = my * inv_rho;
@@ -191,7 +218,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const R div = (sfx[f][lr][lc] - sfx[f][lr][lc + 1]) + (sfy[f][lr][lc] - sfy[f][lr + 1][lc]);
-            Un[f] = Uin[f * N + c] + dt_dV * div;
+            Un[f] = sc[f][lr][lc] + dt_dV * div;
         }
         const R rP = sp[0][lr + 2][lc + 2];
         const R rhoP = DEV ? (R)1 + rP : rP;

@@ -71,6 +71,7 @@ class Info(C.Structure):
         ("tile_x", C.c_int),
         ("tile_y", C.c_int),
         ("tile_z", C.c_int),
+        ("tune_ms", C.c_double * 8),
     ]
 
 
