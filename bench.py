@@ -56,6 +56,55 @@ def time_path(rt, torch, precision, steps, warmup):
     return dict(solver=s, event_ms=ms, wall_s=wall, nu=nu, res=res)
 
 
+def batch_bench(rt, torch, steps, warmup):
+    """256 seeded cavities (sides 64..512, Ra 1e3..1e7, Pr 0.71/7, uniform or
+    tanh): the batched handle (one launch per step over all members) against
+    the same 256 problems stepped as separate single-domain handles."""
+    from paper_2202_13449_amd.workloads import (CAVITY_GRAVITY, CAVITY_KIND, CAVITY_TDEV, batch_cavities,
+                                                total_cells)
+
+    members = batch_cavities()
+    cells = total_cells(members)
+    meshes = [rt.make_mesh(2, (m["n"], m["n"]), (m["stretch"], m["stretch"])) for m in members]
+    bcs = [rt.make_bc(CAVITY_KIND, CAVITY_TDEV, CAVITY_GRAVITY) for _ in members]
+    b = rt.Batch(meshes, [m["Ra"] for m in members], [m["Pr"] for m in members], bcs, Ma=MA,
+                 precision=rt.FP32_DEV, seed=4, noise_amp=1e-6, residual_every=100, mass_fix_every=1000)
+    stream = torch.cuda.current_stream()
+    b.step(warmup)
+    b.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    b.sync()
+    ms_batch = e0.elapsed_time(e1) / steps
+    del b
+    torch.cuda.empty_cache()
+    singles = [rt.Solver(2, (m["n"], m["n"]), (m["stretch"], m["stretch"]), CAVITY_KIND, CAVITY_TDEV,
+                         CAVITY_GRAVITY, Ra=m["Ra"], Pr=m["Pr"], Ma=MA, precision=rt.FP32_DEV, seed=4,
+                         noise_amp=1e-6, residual_every=100, mass_fix_every=1000) for m in members]
+    seq_steps = max(100, steps // 10)
+    for s in singles:
+        s.step(100)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for s in singles:
+        s.step(seq_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1) / seq_steps
+    bpl = BYTES_PER_CELL["f32"] * cells
+    return {"metric": "cell-updates/s", "workload": "256 batched 2D cavities (seed 4), FP32 deviation",
+            "cells": cells, "steps": steps, "warmup": warmup,
+            "batched": {"ms_per_step": ms_batch, "value": cells / (ms_batch * 1e-3),
+                        "hbm_gbs": bpl / (ms_batch * 1e-3) / 1e9,
+                        "frac": bpl / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "sequential_256_handles": {"ms_per_step": ms_seq, "value": cells / (ms_seq * 1e-3),
+                                       "steps": seq_steps},
+            "speedup_batched_vs_sequential": ms_seq / ms_batch}
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle, as written, on a bounded sample of the same workload."""
     from oracle import Oracle, OracleConfig, physics_from_ra, mesh_nodes
@@ -85,6 +134,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
+    ap.add_argument("--batch", action="store_true",
+                    help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -106,6 +157,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
+        return
+    if args.batch:
+        print(json.dumps(batch_bench(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE
     r32 = time_path(rt, torch, rt.FP32_DEV, args.steps, args.warmup)

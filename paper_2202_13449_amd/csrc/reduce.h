@@ -127,6 +127,7 @@ __global__ void __launch_bounds__(256) k_nusselt(Domain d, const R *__restrict__
     }
 }
 
+template <int Unused = 0>
 __global__ void __launch_bounds__(256) k_nusselt_finalize(const double *__restrict__ parts, int nparts,
                                                           double *__restrict__ out) {
     __shared__ double sred[6 * 4 + 8];
@@ -182,6 +183,25 @@ __global__ void __launch_bounds__(256) k_integrals(Domain d, const R *__restrict
     block_sums<kIntParts>(acc, sred);
     if (threadIdx.x == 0)
         for (int k = 0; k < kIntParts; ++k) parts[(int64_t)blockIdx.x * kIntParts + k] = acc[k];
+}
+
+// Per-segment sums: out[m*K + k] = sum over rows [begin[m], begin[m+1]) of
+// parts[row*K + k]; one block per segment, fixed order.
+template <int K>
+__global__ void __launch_bounds__(256) k_segment_sum(const double *__restrict__ parts, const int *__restrict__ begin,
+                                                     double *__restrict__ out) {
+    __shared__ double sred[K * 4];
+    const int m = blockIdx.x;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int b = begin[m] + threadIdx.x; b < begin[m + 1]; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += parts[(int64_t)b * K + k];
+    block_sums<K>(acc, sred);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[(int64_t)m * K + k] = acc[k];
 }
 
 // Subtract the uniform density shift (sum r dV - M0)/V from r (FP32 path).

@@ -16,8 +16,10 @@
 #include "rtlbfs_device.h"
 #include "step2d.h"
 #include "step3d.h"
+#include "host_common.h"
 
 using namespace rtlbfs;
+using namespace rtlbfs::host;
 
 // ----------------------------------------------------------------- kernels --
 
@@ -51,43 +53,12 @@ constexpr int kTX2 = 32, kTY2 = 8;             // largest 2D tile (sizes the par
 constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per cell)
 constexpr int kRedBlocks = 512;                // blocks of the diagnostics kernels
 
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
-double splitmix_uniform(uint64_t seed, uint64_t i) {
-    // SplitMix64 (Steele, Lea & Flood 2014): i-th output of the generator
-    // seeded with `seed`, top 53 bits to [0, 1), then to [-1, 1).
-    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    z ^= z >> 31;
-    return 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
-}
-
-int mesh_nodes(int n, double stretch, double *x, double *L) {
-    if (n < 1 || !x) return RTLBFS_EINVAL;
-    if (!(stretch > 0.0)) {
-        for (int i = 0; i <= n; ++i) x[i] = i;
-        if (L) *L = n;
-        return RTLBFS_OK;
-    }
-    // Eq. 74 on the unit interval, rescaled so the finest cell has size 1.
-    const double th = std::tanh(stretch);
-    for (int i = 0; i <= n; ++i) x[i] = 0.5 * (th + std::tanh(2.0 * stretch * ((double)i / n - 0.5))) / th;
-    double hmin = 1e300;
-    for (int i = 0; i < n; ++i) hmin = std::min(hmin, x[i + 1] - x[i]);
-    const double len = 1.0 / hmin;
-    for (int i = 0; i <= n; ++i) x[i] *= len;
-    if (L) *L = len;
-    return RTLBFS_OK;
-}
-
 struct Layout {
-    size_t off_U[2], off_w, off_parts, off_red, bytes;
+    size_t off_U[2], off_w, off_geo, off_parts, off_red, bytes;
     int64_t cells;
     int nparts;
 };
 
-int elem_size(int precision) { return precision == RTLBFS_FP32_DEV ? 4 : 8; }
 
 int step_blocks(const rtlbfs_mesh &m, int tile = 0) {
     if (m.dim == 2) {
@@ -97,7 +68,6 @@ int step_blocks(const rtlbfs_mesh &m, int tile = 0) {
     return ((m.n[0] + kTX3 - 1) / kTX3) * ((m.n[1] + kTY3 - 1) / kTY3) * ((m.n[2] + kTZ3 - 1) / kTZ3);
 }
 
-int64_t field_stride(int64_t cells) { return (cells + 63) / 64 * 64; }
 
 Layout make_layout(const rtlbfs_mesh &m, int precision) {
     Layout l{};
@@ -113,6 +83,8 @@ Layout make_layout(const rtlbfs_mesh &m, int precision) {
     off += copy_bytes;
     l.off_w = off;
     off += align256(sizeof(double) * (m.n[0] + m.n[1] + (m.dim == 3 ? m.n[2] : 0)));
+    l.off_geo = off;
+    off += geometry_bytes(m, precision);
     l.nparts = kRedBlocks;
     for (int t = 0; t < (m.dim == 2 ? kNumTiles2 : 1); ++t) l.nparts = std::max(l.nparts, step_blocks(m, t));
     l.off_parts = off;
@@ -176,43 +148,6 @@ int hip_fail(rtlbfs_t h, hipError_t e, const char *what) {
         hipError_t _e = (call);                                \
         if (_e != hipSuccess) return hip_fail((h), _e, #call); \
     } while (0)
-
-int heat_axis(const rtlbfs_mesh &m, const rtlbfs_bc &bc) {
-    for (int a = 0; a < m.dim; ++a)
-        if (bc.kind[2 * a] == RTLBFS_WALL_ISOTHERMAL && bc.kind[2 * a + 1] == RTLBFS_WALL_ISOTHERMAL) return a;
-    return -1;
-}
-
-int validate(const rtlbfs_mesh *m, const rtlbfs_bc *bc, const rtlbfs_opts &o, double Ra, double Pr, double Ma,
-             std::string &why) {
-    if (!m || !bc) return why = "mesh or bc is NULL", RTLBFS_EINVAL;
-    if (m->dim != 2 && m->dim != 3) return why = "dim must be 2 or 3", RTLBFS_EINVAL;
-    for (int a = 0; a < m->dim; ++a) {
-        if (m->n[a] < 4) return why = "each axis needs >= 4 cells", RTLBFS_EINVAL;
-        if (m->n[a] > (1 << 20)) return why = "axis too long", RTLBFS_EINVAL;
-        const int k0 = bc->kind[2 * a], k1 = bc->kind[2 * a + 1];
-        for (int k : {k0, k1})
-            if (k != RTLBFS_PERIODIC && k != RTLBFS_WALL_ISOTHERMAL && k != RTLBFS_WALL_ADIABATIC)
-                return why = "unknown boundary kind", RTLBFS_EINVAL;
-        if ((k0 == RTLBFS_PERIODIC) != (k1 == RTLBFS_PERIODIC))
-            return why = "periodic sides must come in pairs", RTLBFS_EINVAL;
-        if (k0 == RTLBFS_PERIODIC && m->stretch[a] > 0.0)
-            return why = "periodic axes must be uniform", RTLBFS_EINVAL;
-        if (!(m->stretch[a] >= 0.0) || m->stretch[a] > 10.0) return why = "stretch out of range", RTLBFS_EINVAL;
-    }
-    if (bc->gravity_axis < -1 || bc->gravity_axis >= m->dim) return why = "gravity_axis out of range", RTLBFS_EINVAL;
-    if (o.precision != RTLBFS_FP64_PLAIN && o.precision != RTLBFS_FP32_DEV && o.precision != RTLBFS_FP64_DEV)
-        return why = "unknown precision", RTLBFS_EINVAL;
-    if (o.phys_given) {
-        if (!(o.nu > 0.0) || !(o.chi > 0.0) || !(o.beta_g >= 0.0)) return why = "nu, chi > 0, beta_g >= 0", RTLBFS_EINVAL;
-    } else {
-        if (!(Ra > 0.0) || !(Pr > 0.0)) return why = "Ra and Pr must be > 0", RTLBFS_EINVAL;
-        if (!(Ma > 0.0) || Ma > 0.3) return why = "Ma must be in (0, 0.3]", RTLBFS_EINVAL;
-    }
-    if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return why = "dtl and dt must be >= 0", RTLBFS_EINVAL;
-    if (o.init != RTLBFS_INIT_REST && o.init != RTLBFS_INIT_CONDUCTION) return why = "unknown init", RTLBFS_EINVAL;
-    return RTLBFS_OK;
-}
 
 template <typename R>
 void to_storage(const std::vector<double> &src, std::vector<char> &dst) {
@@ -440,79 +375,32 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
     else rtlbfs_opts_init(&o);
     std::string why;
     g_create_err.clear();
-    int rc = validate(mesh, bc, o, Ra, Pr, Ma, why);
+    Problem P;
+    int rc = setup_problem(mesh, bc, o, Ra, Pr, Ma, P, why);
     if (rc != RTLBFS_OK) {
         g_create_err = why;
         return rc;
     }
     rtlbfs_t h = new (std::nothrow) rtlbfs_handle();
     if (!h) return RTLBFS_ENOMEM;
-    h->mesh = *mesh;
-    if (h->mesh.dim == 2) {
-        h->mesh.n[2] = 1;
-        h->mesh.stretch[2] = 0.0;
-    }
+    h->mesh = P.mesh;
     h->bc = *bc;
     if (o.residual_every <= 0) o.residual_every = 100;
     if (o.mass_fix_every == 0) o.mass_fix_every = 1000;
     h->opts = o;
+    h->opts.dtl = P.dtl;
+    h->opts.dt = P.dt;
+    h->opts.nu = P.nu;
+    h->opts.chi = P.chi;
+    h->opts.beta_g = P.bg;
     h->stream = (hipStream_t)hip_stream;
     h->lay = make_layout(h->mesh, o.precision);
-
-    // Mesh and lengths.
-    const int D = h->mesh.dim;
-    std::vector<double> widths;
-    for (int a = 0; a < D; ++a) {
-        std::vector<double> x(h->mesh.n[a] + 1);
-        mesh_nodes(h->mesh.n[a], h->mesh.stretch[a], x.data(), &h->length[a]);
-        for (int i = 0; i < h->mesh.n[a]; ++i) widths.push_back(x[i + 1] - x[i]);
-    }
-    const int ha = heat_axis(h->mesh, *bc);
-    const int la = ha >= 0 ? ha : (bc->gravity_axis >= 0 ? bc->gravity_axis : 0);
-    h->L = h->length[la];
-
-    // Eq. 63 with V_c = Ma, dT = 1 (or the given physics), Eqs. 9-10.
-    double nu, chi, bg;
-    if (o.phys_given) {
-        nu = o.nu;
-        chi = o.chi;
-        bg = o.beta_g;
-    } else {
-        nu = Ma * h->L * std::sqrt(Pr / Ra);
-        chi = nu / Pr;
-        bg = Ma * Ma / h->L;
-    }
-    const double dtl = o.dtl > 0.0 ? o.dtl : 1.0;
-    const double dt = o.dt > 0.0 ? o.dt : std::min(0.5, 0.15 / std::max(nu, chi));
-    h->opts.dtl = dtl;
-    h->opts.dt = dt;
-    h->opts.nu = nu;
-    h->opts.chi = chi;
-    h->opts.beta_g = bg;
-
+    const int D = P.D;
+    for (int a = 0; a < 3; ++a) h->length[a] = P.length[a];
+    h->L = P.L;
+    const std::vector<double> &widths = P.widths;
     Domain &d = h->dom;
-    std::memset(&d, 0, sizeof(d));
-    d.dim = D;
-    for (int a = 0; a < 3; ++a) {
-        d.n[a] = a < D ? h->mesh.n[a] : 1;
-        d.periodic[a] = a < D ? bc->kind[2 * a] == RTLBFS_PERIODIC : 1;
-    }
-    const bool dev = o.precision != RTLBFS_FP64_PLAIN;
-    for (int s = 0; s < 6; ++s) {
-        d.kind[s] = s < 2 * D ? bc->kind[s] : RTLBFS_PERIODIC;
-        d.Tw[s] = dev ? bc->Tdev[s] : kT0 + bc->Tdev[s];
-    }
-    d.gaxis = bc->gravity_axis;
-    d.force_pred = o.buoyancy_update_only ? 0 : 1;
-    d.nu = nu;
-    d.chi = chi;
-    d.bg = bg;
-    d.dtl = dtl;
-    d.dt = dt;
-    d.tau_f = 0.5 + nu / (kCs2 * dtl);
-    d.tau_g = 0.5 + chi / (kCs2 * dtl);
-    d.cells = h->lay.cells;
-    d.fstride = field_stride(d.cells);
+    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, d);
 
     // Workspace.
     if (workspace) {
@@ -539,9 +427,14 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
             d.w[a] = wdev + off;
             off += h->mesh.n[a];
         }
+        std::vector<char> geo;
+        size_t goff[3] = {0, 0, 0};
+        pack_geometry(P, o.precision, geo, goff);
+        for (int a = 0; a < D; ++a) d.geo[a] = h->ws + h->lay.off_geo + goff[a];
         hipError_t e = hipMemcpy(wdev, widths.data(), widths.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(h->ws + h->lay.off_geo, geo.data(), geo.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            int r2 = hip_fail(h, e, "upload widths");
+            int r2 = hip_fail(h, e, "upload geometry");
             rtlbfs_destroy(h);
             return r2;
         }
@@ -556,26 +449,10 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
         }
     }
 
-    // Seeded initial state (absolute primitives on the host, then storage).
+    // Seeded initial state: rho = 1, u = 0, T - T0 from the profile and noise.
     const int64_t N = h->lay.cells;
-    std::vector<double> centre;  // cell centres of the heat axis
-    if (ha >= 0) {
-        std::vector<double> x(h->mesh.n[ha] + 1);
-        mesh_nodes(h->mesh.n[ha], h->mesh.stretch[ha], x.data(), nullptr);
-        for (int i = 0; i < h->mesh.n[ha]; ++i) centre.push_back(0.5 * (x[i] + x[i + 1]));
-    }
-    std::vector<double> rho((size_t)N, 1.0), u((size_t)N * D, 0.0), T((size_t)N);
-    for (int64_t c = 0; c < N; ++c) {
-        double Tp = 0.0;
-        if (o.init == RTLBFS_INIT_CONDUCTION && ha >= 0) {
-            const int64_t stride = ha == 0 ? 1 : (ha == 1 ? h->mesh.n[0] : (int64_t)h->mesh.n[0] * h->mesh.n[1]);
-            const int i = (int)((c / stride) % h->mesh.n[ha]);
-            const double xi = centre[i] / h->length[ha];
-            Tp = bc->Tdev[2 * ha] + (bc->Tdev[2 * ha + 1] - bc->Tdev[2 * ha]) * xi;
-        }
-        Tp += o.noise_amp * splitmix_uniform(o.seed, (uint64_t)c);
-        T[c] = Tp;  // deviation T - T0
-    }
+    std::vector<double> rho((size_t)N, 1.0), u((size_t)N * D, 0.0), T;
+    initial_Tdev(P, o, T);
     rc = upload_prims(h, rho.data(), u.data(), T.data());
     if (rc != RTLBFS_OK) {
         rtlbfs_destroy(h);
@@ -689,7 +566,7 @@ int rtlbfs_nusselt(rtlbfs_t h, rtlbfs_nu *out) {
             break;
     }
     HIP_TRY(h, hipGetLastError());
-    k_nusselt_finalize<<<1, 256, 0, h->stream>>>(parts, kRedBlocks, h->nu_out());
+    k_nusselt_finalize<0><<<1, 256, 0, h->stream>>>(parts, kRedBlocks, h->nu_out());
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipMemcpyAsync(h->host_buf + 8, h->nu_out(), 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));

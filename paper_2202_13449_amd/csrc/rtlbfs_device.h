@@ -14,6 +14,14 @@ constexpr int kPartials = 5;        // residual partial sums per block
 
 enum : int { kPeriodic = 0, kIsothermal = 1, kAdiabatic = 2 };
 
+// Per-axis geometry, stored as kGeoFields arrays of n values (SoA) in the
+// precision of the step kernel: the cell width, its inverse, and the Eq. 56
+// inverse-distance weights of the low face (phi_S = lo_self * phi_P +
+// lo_nb * phi_{P-1}) and of the high face (phi_S = hi_self * phi_P + hi_nb *
+// phi_{P+1}).  Periodic axes use the wrapped neighbour; weights of wall faces
+// are unused.
+enum : int { kGeoW = 0, kGeoInvW, kGeoLoSelf, kGeoLoNb, kGeoHiSelf, kGeoHiNb, kGeoFields };
+
 // One structured domain as the kernels see it.  Lengths in lattice units;
 // Tw is in the storage convention (T - T0 for deviation storage, absolute T
 // for plain storage).
@@ -26,9 +34,11 @@ struct Domain {
     int gaxis;        // buoyancy along +gaxis, -1 none
     int force_pred;   // 1: buoyancy also in the predicted momentum
     double nu, chi, bg, dtl, dt, tau_f, tau_g;
-    const double *w[3];  // cell widths per axis (device)
+    const double *w[3];  // cell widths per axis (device, FP64; diagnostics)
+    const void *geo[3];  // per-axis geometry records in the kernel precision (see kGeo*)
     int64_t cells;       // number of cells
     int64_t fstride;     // elements between consecutive fields of one state copy
+    void *U[2];          // the two state copies (used by the batched kernels)
 };
 
 // ------------------------------------------------------------ reductions --

@@ -45,15 +45,33 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     __shared__ R sfx[4][TY][TX + 1];
     __shared__ R sfy[4][TY + 1][TX];
     __shared__ R sc[4][TY][TX];  // old conserved state of the tile cells
+    __shared__ R sgx[kGeoFields][PX];  // geometry of the tile columns (with halo)
+    __shared__ R sgy[kGeoFields][PY];  // geometry of the tile rows (with halo)
     __shared__ double sred[kPartials * 16];
 
     const int nx = d.n[0], ny = d.n[1];
     const int64_t N = d.fstride;
     const bool px = d.periodic[0], py = d.periodic[1];
-    const double *__restrict__ wx = d.w[0];
-    const double *__restrict__ wy = d.w[1];
+    const R *__restrict__ geox = (const R *)d.geo[0];
+    const R *__restrict__ geoy = (const R *)d.geo[1];
     const Phys<R> ph = make_phys<R>(d);
     const int tid = threadIdx.x, nthr = blockDim.x;
+
+    // Phase 1a: geometry of the halo columns and rows.
+    for (int q = tid; q < PX + PY; q += nthr) {
+        const bool isx = q < PX;
+        const int l = isx ? q : q - PX;
+        const int n = isx ? nx : ny;
+        int g = (isx ? i0 : j0) - 2 + l;
+        if (isx ? px : py) g = wrap(g, n);
+        if (g < 0 || g >= n) continue;
+        const R *src = isx ? geox : geoy;
+#pragma unroll
+        for (int k = 0; k < kGeoFields; ++k) {
+            if (isx) sgx[k][l] = src[k * n + g];
+            else sgy[k][l] = src[k * n + g];
+        }
+    }
 
     // Phase 1: load + primitives.
     for (int q = tid; q < PX * PY; q += nthr) {
@@ -87,13 +105,11 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
         if (py) gj = wrap(gj, ny);
         if (gi < 0 || gi >= nx || gj < 0 || gj >= ny) continue;
         const int ci = li + 1, cj = lj + 1;  // position in sp
-        const R wP = (R)wx[gi], hP = (R)wy[gj];
         const bool wall_w = !px && gi == 0, wall_e = !px && gi == nx - 1;
         const bool wall_s = !py && gj == 0, wall_n = !py && gj == ny - 1;
-        const R ww = wall_w ? (R)0 : (R)wx[px ? wrap(gi - 1, nx) : gi - 1];
-        const R we = wall_e ? (R)0 : (R)wx[px ? wrap(gi + 1, nx) : gi + 1];
-        const R hs = wall_s ? (R)0 : (R)wy[py ? wrap(gj - 1, ny) : gj - 1];
-        const R hn = wall_n ? (R)0 : (R)wy[py ? wrap(gj + 1, ny) : gj + 1];
+        const R xls = sgx[kGeoLoSelf][ci], xln = sgx[kGeoLoNb][ci], xhs = sgx[kGeoHiSelf][ci], xhn = sgx[kGeoHiNb][ci];
+        const R yls = sgy[kGeoLoSelf][cj], yln = sgy[kGeoLoNb][cj], yhs = sgy[kGeoHiSelf][cj], yhn = sgy[kGeoHiNb][cj];
+        const R ixP = sgx[kGeoInvW][ci], iyP = sgy[kGeoInvW][cj];
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const R vP = sp[p][cj][ci];
@@ -103,12 +119,13 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                 if (p < 3) return (R)0;
                 return d.kind[side] == kIsothermal ? (R)d.Tw[side] : vP;
             };
-            const R fw = wall_w ? wallv(0) : (vP * ww + sp[p][cj][ci - 1] * wP) / (wP + ww);
-            const R fe = wall_e ? wallv(1) : (vP * we + sp[p][cj][ci + 1] * wP) / (wP + we);
-            const R fs = wall_s ? wallv(2) : (vP * hs + sp[p][cj - 1][ci] * hP) / (hP + hs);
-            const R fnn = wall_n ? wallv(3) : (vP * hn + sp[p][cj + 1][ci] * hP) / (hP + hn);
-            sg[p][0][lj][li] = (fe - fw) / wP;
-            sg[p][1][lj][li] = (fnn - fs) / hP;
+            // Eq. 56 face values with precomputed inverse-distance weights
+            const R fw = wall_w ? wallv(0) : vP * xls + sp[p][cj][ci - 1] * xln;
+            const R fe = wall_e ? wallv(1) : vP * xhs + sp[p][cj][ci + 1] * xhn;
+            const R fs = wall_s ? wallv(2) : vP * yls + sp[p][cj - 1][ci] * yln;
+            const R fnn = wall_n ? wallv(3) : vP * yhs + sp[p][cj + 1][ci] * yhn;
+            sg[p][0][lj][li] = (fe - fw) * ixP;
+            sg[p][1][lj][li] = (fnn - fs) * iyP;
         }
     }
     __syncthreads();
@@ -121,14 +138,14 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
             const int lf = q % (TX + 1), lr = q / (TX + 1);
             const int gf = i0 + lf, gj = j0 + lr;
             if (gj >= ny || gf > nx) continue;
-            const R area = (R)wy[gj];
+            const R area = sgy[kGeoW][lr + 2];
             if (!px && (gf == 0 || gf == nx)) {
                 const int side = gf == 0 ? 0 : 1;
                 const int ci = gf == 0 ? lf + 2 : lf + 1;  // the wall cell in sp
                 const R sgn = gf == 0 ? (R)-1 : (R)1;
                 const R rP = sp[0][lr + 2][ci];
                 const R rho = DEV ? (R)1 + rP : rP;
-                const R d_w = (R)0.5 * (R)wx[gf == 0 ? 0 : nx - 1];
+                const R d_w = (R)0.5 * sgx[kGeoW][ci];
                 const R mloc[2] = {rho * sp[1][lr + 2][ci], rho * sp[2][lr + 2][ci]};
                 wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][lr + 2][ci], sgn, d_w, d.kind[side] == kIsothermal,
                                      (R)d.Tw[side], ph, F);
@@ -144,8 +161,8 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                     B.g[0][p] = sg[p][0][lr + 1][lf + 1];
                     B.g[1][p] = sg[p][1][lr + 1][lf + 1];
                 }
-                const R dL = (R)0.5 * (R)wx[px ? wrap(gf - 1, nx) : gf - 1];
-                const R dR = (R)0.5 * (R)wx[px ? wrap(gf, nx) : gf];
+                const R dL = (R)0.5 * sgx[kGeoW][lf + 1];
+                const R dR = (R)0.5 * sgx[kGeoW][lf + 2];
                 const R fdir[2] = {(d.force_pred && d.gaxis == 0) ? (R)1 : (R)0,
                                    (d.force_pred && d.gaxis == 1) ? (R)1 : (R)0};
                 face_flux<R, 2, DEV>(A, B, dL, dR, fdir, ph, F);
@@ -159,7 +176,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
             const int lc = qq % TX, lf = qq / TX;
             const int gi = i0 + lc, gf = j0 + lf;
             if (gi >= nx || gf > ny) continue;
-            const R area = (R)wx[gi];
+            const R area = sgx[kGeoW][lc + 2];
             R G[4];
             if (!py && (gf == 0 || gf == ny)) {
                 const int side = gf == 0 ? 2 : 3;
@@ -167,7 +184,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                 const R sgn = gf == 0 ? (R)-1 : (R)1;
                 const R rP = sp[0][cj][lc + 2];
                 const R rho = DEV ? (R)1 + rP : rP;
-                const R d_w = (R)0.5 * (R)wy[gf == 0 ? 0 : ny - 1];
+                const R d_w = (R)0.5 * sgy[kGeoW][cj];
                 // normal = y: m_a = m_y, m_b = m_x
                 const R mloc[2] = {rho * sp[2][cj][lc + 2], rho * sp[1][cj][lc + 2]};
                 wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][cj][lc + 2], sgn, d_w, d.kind[side] == kIsothermal,
@@ -186,8 +203,8 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                     B.g[0][p] = sg[pp][1][lf + 1][lc + 1];
                     B.g[1][p] = sg[pp][0][lf + 1][lc + 1];
                 }
-                const R dL = (R)0.5 * (R)wy[py ? wrap(gf - 1, ny) : gf - 1];
-                const R dR = (R)0.5 * (R)wy[py ? wrap(gf, ny) : gf];
+                const R dL = (R)0.5 * sgy[kGeoW][lf + 1];
+                const R dR = (R)0.5 * sgy[kGeoW][lf + 2];
                 const R fdir[2] = {(d.force_pred && d.gaxis == 1) ? (R)1 : (R)0,
                                    (d.force_pred && d.gaxis == 0) ? (R)1 : (R)0};
                 face_flux<R, 2, DEV>(A, B, dL, dR, fdir, ph, G);
@@ -213,7 +230,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
         const int gi = i0 + lc, gj = j0 + lr;
         if (gi >= nx || gj >= ny) continue;
         const int64_t c = (int64_t)gj * nx + gi;
-        const R dt_dV = dtR / ((R)wx[gi] * (R)wy[gj]);
+        const R dt_dV = dtR * sgx[kGeoInvW][lc + 2] * sgy[kGeoInvW][lr + 2];
         R Un[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {

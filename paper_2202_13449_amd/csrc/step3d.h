@@ -33,6 +33,9 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     __shared__ R sf1[NPRIM][TL::NF1];
     __shared__ R sf2[NPRIM][TL::NF2];
     __shared__ double sred[kPartials * 16];
+    __shared__ R sgeo0[kGeoFields][TL::PX];
+    __shared__ R sgeo1[kGeoFields][TL::PY];
+    __shared__ R sgeo2[kGeoFields][TL::PZ];
 
     const int n[3] = {d.n[0], d.n[1], d.n[2]};
     const int org[3] = {i0, j0, k0};
@@ -44,6 +47,27 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         inside = c >= 0 && c < n[a];
         return c;
     };
+
+    // geometry of axis a, halo position l (l = global index - origin + 2)
+    auto geo = [&](int a, int k, int l) -> R {
+        return a == 0 ? sgeo0[k][l] : (a == 1 ? sgeo1[k][l] : sgeo2[k][l]);
+    };
+    // Phase 1a: geometry of the halo lines of the three axes.
+    for (int q = tid; q < TL::PX + TL::PY + TL::PZ; q += nthr) {
+        const int a = q < TL::PX ? 0 : (q < TL::PX + TL::PY ? 1 : 2);
+        const int l = a == 0 ? q : (a == 1 ? q - TL::PX : q - TL::PX - TL::PY);
+        bool inside;
+        const int g = gcell(org[a] - 2 + l, a, inside);
+        if (!inside) continue;
+        const R *src = (const R *)d.geo[a];
+#pragma unroll
+        for (int k = 0; k < kGeoFields; ++k) {
+            const R v = src[k * n[a] + g];
+            if (a == 0) sgeo0[k][l] = v;
+            else if (a == 1) sgeo1[k][l] = v;
+            else sgeo2[k][l] = v;
+        }
+    }
 
     // Phase 1: load + primitives.
     for (int q = tid; q < TL::NP; q += nthr) {
@@ -72,13 +96,13 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         g[2] = gcell(k0 - 1 + lz, 2, in[2]);
         if (!(in[0] && in[1] && in[2])) continue;
         const int pc = TL::pidx(lx + 1, ly + 1, lz + 1);
-#pragma unroll
+        const int lpos[3] = {lx + 1, ly + 1, lz + 1};  // positions in the halo lines
         for (int a = 0; a < 3; ++a) {
             const int step = a == 0 ? 1 : (a == 1 ? TL::PX : TL::PX * TL::PY);
-            const R wP = (R)d.w[a][g[a]];
+            const R iwP = geo(a, kGeoInvW, lpos[a]);
             const bool wlo = !d.periodic[a] && g[a] == 0, whi = !d.periodic[a] && g[a] == n[a] - 1;
-            const R wl = wlo ? (R)0 : (R)d.w[a][d.periodic[a] ? wrap(g[a] - 1, n[a]) : g[a] - 1];
-            const R wh = whi ? (R)0 : (R)d.w[a][d.periodic[a] ? wrap(g[a] + 1, n[a]) : g[a] + 1];
+            const R ls = geo(a, kGeoLoSelf, lpos[a]), ln = geo(a, kGeoLoNb, lpos[a]);
+            const R hs = geo(a, kGeoHiSelf, lpos[a]), hn = geo(a, kGeoHiNb, lpos[a]);
 #pragma unroll
             for (int p = 0; p < NPRIM; ++p) {
                 const R vP = sp[p][pc];
@@ -87,9 +111,10 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                     if (p < 4) return (R)0;
                     return d.kind[side] == kIsothermal ? (R)d.Tw[side] : vP;
                 };
-                const R flo = wlo ? wallv(2 * a) : (vP * wl + sp[p][pc - step] * wP) / (wP + wl);
-                const R fhi = whi ? wallv(2 * a + 1) : (vP * wh + sp[p][pc + step] * wP) / (wP + wh);
-                sg[p][a][q] = (fhi - flo) / wP;
+                // Eq. 56 face values with precomputed inverse-distance weights
+                const R flo = wlo ? wallv(2 * a) : vP * ls + sp[p][pc - step] * ln;
+                const R fhi = whi ? wallv(2 * a + 1) : vP * hs + sp[p][pc + step] * hn;
+                sg[p][a][q] = (fhi - flo) * iwP;
             }
         }
     }
@@ -127,7 +152,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         const int gf = org[ax] + f[ax];
         R area = (R)1;
         for (int a = 0; a < 3; ++a)
-            if (a != ax) area *= (R)d.w[a][org[a] + f[a]];
+            if (a != ax) area *= geo(a, kGeoW, f[a] + 2);
         R F[5];
         const int cR[3] = {f[0], f[1], f[2]};
         int cL[3] = {f[0], f[1], f[2]};
@@ -139,7 +164,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
             const R sgn = gf == 0 ? (R)-1 : (R)1;
             const R rP = sp[0][pc];
             const R rho = DEV ? (R)1 + rP : rP;
-            const R d_w = (R)0.5 * (R)d.w[ax][gf == 0 ? 0 : n[ax] - 1];
+            const R d_w = (R)0.5 * geo(ax, kGeoW, cw[ax] + 2);
             const R mloc[3] = {rho * sp[1 + ax_loc[0]][pc], rho * sp[1 + ax_loc[1]][pc], rho * sp[1 + ax_loc[2]][pc]};
             R G[5];
             wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, d.kind[side] == kIsothermal, (R)d.Tw[side],
@@ -163,9 +188,8 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                     B.g[k][p] = sg[pmap[p]][ax_loc[k]][gR];
                 }
             }
-            const int gl = org[ax] + cL[ax], gr = gf;
-            const R dL = (R)0.5 * (R)d.w[ax][d.periodic[ax] ? wrap(gl, n[ax]) : gl];
-            const R dR = (R)0.5 * (R)d.w[ax][d.periodic[ax] ? wrap(gr, n[ax]) : gr];
+            const R dL = (R)0.5 * geo(ax, kGeoW, cL[ax] + 2);
+            const R dR = (R)0.5 * geo(ax, kGeoW, cR[ax] + 2);
             R fdir[3];
             for (int k = 0; k < 3; ++k) fdir[k] = (d.force_pred && d.gaxis == ax_loc[k]) ? (R)1 : (R)0;
             R G[5];
@@ -195,7 +219,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         const int gx = i0 + x, gy = j0 + y, gz = k0 + z;
         if (gx >= n[0] || gy >= n[1] || gz >= n[2]) continue;
         const int64_t c = ((int64_t)gz * n[1] + gy) * n[0] + gx;
-        const R dt_dV = dtR / ((R)d.w[0][gx] * (R)d.w[1][gy] * (R)d.w[2][gz]);
+        const R dt_dV = dtR * sgeo0[kGeoInvW][x + 2] * sgeo1[kGeoInvW][y + 2] * sgeo2[kGeoInvW][z + 2];
         const int o0 = (z * TY + y) * (TX + 1) + x;
         const int o1 = (z * (TY + 1) + y) * TX + x;
         const int o2 = (z * TY + y) * TX + x;
