@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -105,6 +107,85 @@ def batch_bench(rt, torch, steps, warmup):
             "speedup_batched_vs_sequential": ms_seq / ms_batch}
 
 
+def timed(torch, solver, steps):
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    solver.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    solver.sync()
+    return e0.elapsed_time(e1) / steps
+
+
+def rb_bench(rt, torch, steps, warmup):
+    """1024 x 512 Rayleigh-Benard box, periodic in x, Ra = 1e8 on H = 512,
+    conduction profile plus 1e-3 seeded noise, FP32 deviation storage: a long
+    unsteady run (stability) and its throughput."""
+    s = rt.Solver(2, (1024, 512), (0, 0), (0, 0, 1, 1), (0, 0, 0.5, -0.5), 1, Ra=1e8, Pr=0.71, Ma=MA,
+                  precision=rt.FP32_DEV, init=rt.INIT_CONDUCTION, seed=3, noise_amp=1e-3)
+    s.step(warmup)
+    ms = timed(torch, s, steps)
+    u, v = s.field(1), s.field(2)
+    umax = float(np.sqrt(u * u + v * v).max())
+    cells = 1024 * 512
+    nu = s.nusselt()
+    return {"workload": "rb1024x512 Ra=1e8 FP32", "cells": cells, "steps": steps + warmup, "ms_per_step": ms,
+            "value": cells / (ms * 1e-3), "hbm_gbs": BYTES_PER_CELL["f32"] * cells / (ms * 1e-3) / 1e9,
+            "finite": bool(np.isfinite(umax)), "umax": umax, "nu": nu,
+            "tile": [s.info.tile_x, s.info.tile_y]}
+
+
+def cube_bench(rt, torch, steps, warmup):
+    """192^3 tanh (phi = 1.8) cubic cavity, Ra = 1e6: FP32 deviation and FP64
+    plain throughput."""
+    out = {"workload": "cube192 tanh1.8 Ra=1e6", "cells": 192 ** 3}
+    for name, prec, bpc in (("fp32_dev", rt.FP32_DEV, 40), ("fp64_plain", rt.FP64_PLAIN, 80)):
+        s = rt.Solver(3, (192, 192, 192), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=1e6,
+                      Pr=0.71, Ma=MA, precision=prec, seed=1, noise_amp=1e-6)
+        s.step(warmup)
+        ms = timed(torch, s, steps)
+        out[name] = {"ms_per_step": ms, "value": 192 ** 3 / (ms * 1e-3),
+                     "hbm_gbs": bpc * 192 ** 3 / (ms * 1e-3) / 1e9, "nu": s.nusselt()}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def steady_bench(rt, torch, steps, warmup, tol=1e-8, max_steps=4_000_000, chunk=20000):
+    """The 256^2 cavity run to steady state: FP64 plain until both Eq. 65
+    ratios are below tol, then FP32 deviation for the same number of steps;
+    Nusselt numbers and velocity maxima of both (the fixed-Nu-error check)."""
+    res = {}
+    s64 = make_solver(rt, rt.FP64_PLAIN)
+    n = 0
+    t0 = time.perf_counter()
+    while n < max_steps:
+        s64.step(chunk)
+        n += chunk
+        if max(s64.residual()) < tol:
+            break
+    res["fp64_plain"] = {"steps": n, "residual": s64.residual(), "nu": s64.nusselt(),
+                         "seconds": time.perf_counter() - t0}
+    s32 = make_solver(rt, rt.FP32_DEV)
+    t0 = time.perf_counter()
+    s32.step(n)
+    res["fp32_dev"] = {"steps": n, "residual": s32.residual(), "nu": s32.nusselt(),
+                       "seconds": time.perf_counter() - t0}
+    a, b = res["fp32_dev"]["nu"], res["fp64_plain"]["nu"]
+    res["nu_rel_diff"] = {k: abs(a[k] - b[k]) / abs(b[k]) for k in b}
+    L = s64.info.L
+    chi = s64.info.chi
+    for name, s in (("fp64_plain", s64), ("fp32_dev", s32)):
+        u = s.grid(s.field(1))
+        v = s.grid(s.field(2))
+        res[name]["umax_mid_uL_over_chi"] = float(0.5 * (u[:, 127] + u[:, 128]).max() * L / chi)
+        res[name]["vmax_mid_vL_over_chi"] = float(0.5 * (v[127, :] + v[128, :]).max() * L / chi)
+    res["workload"] = "cavity256 tanh1.5 Ra=1e6 to steady state"
+    return res
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle, as written, on a bounded sample of the same workload."""
     from oracle import Oracle, OracleConfig, physics_from_ra, mesh_nodes
@@ -136,6 +217,9 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
+    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256"],
+                    help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
+                         "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -160,6 +244,10 @@ def main():
         return
     if args.batch:
         print(json.dumps(batch_bench(rt, torch, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload != "cavity256":
+        fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench}[args.workload]
+        print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE
     r32 = time_path(rt, torch, rt.FP32_DEV, args.steps, args.warmup)

@@ -24,7 +24,7 @@ using namespace rtlbfs::host;
 // ----------------------------------------------------------------- kernels --
 
 template <typename R, bool DEV, int TX, int TY, bool RES>
-__global__ void __launch_bounds__((tile2_threads<TX, TY>())) k_step2d(Domain d, const R *__restrict__ Uin,
+__global__ void __launch_bounds__((tile2_threads<TX, TY>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_step2d(Domain d, const R *__restrict__ Uin,
                                                                     R *__restrict__ Uout, double *__restrict__ parts) {
     const int ntx = (d.n[0] + TX - 1) / TX;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__((tile2_threads<TX, TY>())) k_step2d(Domain d, 
 }
 
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
-__global__ void __launch_bounds__(TX * TY * TZ) k_step3d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
+__global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((amdgpu_waves_per_eu(4, 8))) k_step3d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
                                                 double *__restrict__ parts) {
     const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     tile_step_3d<R, DEV, TX, TY, TZ, RES>(
@@ -50,7 +50,7 @@ struct Tile2 {
 constexpr Tile2 kTiles2[] = {{32, 8}, {16, 16}, {64, 4}, {16, 8}, {8, 8}};
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
 constexpr int kTX2 = 32, kTY2 = 8;             // largest 2D tile (sizes the partials buffer)
-constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per cell)
+constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per face)
 constexpr int kRedBlocks = 512;                // blocks of the diagnostics kernels
 
 struct Layout {
@@ -224,7 +224,7 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
         }
     }
     dim3 grid((d.n[0] + kTX3 - 1) / kTX3, (d.n[1] + kTY3 - 1) / kTY3, (d.n[2] + kTZ3 - 1) / kTZ3);
-    constexpr int nt = kTX3 * kTY3 * kTZ3;
+    constexpr int nt = tile3_threads<kTX3, kTY3, kTZ3>();
     if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
     else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
     return hipGetLastError();

@@ -30,7 +30,7 @@ constexpr int kBTX = 32, kBTY = 8;  // batch tile
 constexpr int kBRedBlocks = 512;
 
 template <typename R, bool DEV, bool RES>
-__global__ void __launch_bounds__((tile2_threads<kBTX, kBTY>())) k_batch_step2d(const Domain *__restrict__ doms,
+__global__ void __launch_bounds__((tile2_threads<kBTX, kBTY>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_batch_step2d(const Domain *__restrict__ doms,
                                                                               const int2 *__restrict__ work, int cur,
                                                                               double *__restrict__ parts) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);

@@ -121,7 +121,7 @@ struct Side {
 // D_k f = (f(+k) - f(-k))/2h, D_kk f = (f(+k) - 2 f(0) + f(-k))/h^2,
 // D_kl f = (f(+k+l) - f(+k-l) - f(-k+l) + f(-k-l))/4h^2.
 template <typename R, int D, bool DEV>
-__device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR, const R (&fdir)[D],
+__host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR, const R (&fdir)[D],
                                  const Phys<R> &ph, R (&out)[D + 2]) {
     constexpr int NP = D + 2;
     const R cs2 = (R)kCs2;
@@ -255,7 +255,7 @@ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> &Rt, R dL
 // conduction -chi (rho T_w - e)/d.  m: momentum in the local frame (m[0]
 // along the wall normal).
 template <typename R, int D, bool DEV>
-__device__ inline void wall_flux(R rP, const R (&m)[D], R eP, R sgn, R d, bool iso, R Tw, const Phys<R> &ph,
+__host__ __device__ inline void wall_flux(R rP, const R (&m)[D], R eP, R sgn, R d, bool iso, R Tw, const Phys<R> &ph,
                                  R (&out)[D + 2]) {
     const R rho = DEV ? (R)1 + rP : rP;
     const R inv_d = (R)1 / d;

@@ -6,6 +6,8 @@
 // partial sums.
 #pragma once
 
+#include <type_traits>
+
 #include "rtlbfs_device.h"
 
 namespace rtlbfs {
@@ -21,6 +23,12 @@ struct Tile3 {
     __device__ static int pidx(int x, int y, int z) { return (z * PY + y) * PX + x; }  // cell at tile coords - 2
     __device__ static int gidx(int x, int y, int z) { return (z * GY + y) * GX + x; }  // cell at tile coords - 1
 };
+
+// One thread per face of the tile, rounded up to whole wavefronts.
+template <int TX, int TY, int TZ>
+constexpr int tile3_threads() {
+    return (((TX + 1) * TY * TZ + TX * (TY + 1) * TZ + TX * TY * (TZ + 1)) + 63) / 64 * 64;
+}
 
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
 __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, int k0, const R *__restrict__ Uin,
@@ -120,94 +128,91 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     }
     __syncthreads();
 
-    // Phase 3: faces of the three axes.
-    for (int q = tid; q < TL::NF0 + TL::NF1 + TL::NF2; q += nthr) {
-        int ax, f[3], qq = q;
-        if (qq < TL::NF0) {
-            ax = 0;
-            f[0] = qq % (TX + 1);
-            f[1] = (qq / (TX + 1)) % TY;
-            f[2] = qq / ((TX + 1) * TY);
-        } else if ((qq -= TL::NF0) < TL::NF1) {
-            ax = 1;
-            f[0] = qq % TX;
-            f[1] = (qq / TX) % (TY + 1);
-            f[2] = qq / (TX * (TY + 1));
-        } else {
-            qq -= TL::NF1;
-            ax = 2;
-            f[0] = qq % TX;
-            f[1] = (qq / TX) % TY;
-            f[2] = qq / (TX * TY);
-        }
-        bool skip = false;
-        for (int a = 0; a < 3; ++a) {
-            const int gcoord = org[a] + f[a];
-            if (a == ax ? gcoord > n[a] : gcoord >= n[a]) skip = true;
-        }
-        if (skip) continue;
-        // local frame: normal ax, then the other axes in increasing order
-        const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
-        const int ax_loc[3] = {ax, t1, t2};
-        const int gf = org[ax] + f[ax];
-        R area = (R)1;
-        for (int a = 0; a < 3; ++a)
-            if (a != ax) area *= geo(a, kGeoW, f[a] + 2);
-        R F[5];
-        const int cR[3] = {f[0], f[1], f[2]};
+    // Phase 3: faces of the three axes (one thread per face; the axis is a
+    // compile-time constant inside face_axis, so no private array is indexed
+    // at run time).
+    auto face_axis = [&](auto AXC, int qq) {
+        constexpr int AX = decltype(AXC)::value;
+        constexpr int T1 = AX == 0 ? 1 : 0, T2 = AX == 2 ? 1 : 2;  // tangents in increasing order
+        constexpr int FX = AX == 0 ? TX + 1 : TX, FY = AX == 1 ? TY + 1 : TY;
+        int f[3];
+        f[0] = qq % FX;
+        f[1] = (qq / FX) % FY;
+        f[2] = qq / (FX * FY);
+        if (org[0] + f[0] > n[0] - (AX == 0 ? 0 : 1)) return;
+        if (org[1] + f[1] > n[1] - (AX == 1 ? 0 : 1)) return;
+        if (org[2] + f[2] > n[2] - (AX == 2 ? 0 : 1)) return;
+        const int gf = org[AX] + f[AX];
+        const R area = geo(T1, kGeoW, f[T1] + 2) * geo(T2, kGeoW, f[T2] + 2);
         int cL[3] = {f[0], f[1], f[2]};
-        cL[ax] -= 1;
-        if (!d.periodic[ax] && (gf == 0 || gf == n[ax])) {
-            const int side = 2 * ax + (gf == 0 ? 0 : 1);
-            const int *cw = gf == 0 ? cR : cL;
-            const int pc = TL::pidx(cw[0] + 2, cw[1] + 2, cw[2] + 2);
+        cL[AX] -= 1;
+        R F[5];
+        if (!d.periodic[AX] && (gf == 0 || gf == n[AX])) {
+            const int side = 2 * AX + (gf == 0 ? 0 : 1);
+            const int wx = gf == 0 ? f[0] : cL[0], wy = gf == 0 ? f[1] : cL[1], wz = gf == 0 ? f[2] : cL[2];
+            const int wa = AX == 0 ? wx : (AX == 1 ? wy : wz);
+            const int pc = TL::pidx(wx + 2, wy + 2, wz + 2);
             const R sgn = gf == 0 ? (R)-1 : (R)1;
             const R rP = sp[0][pc];
             const R rho = DEV ? (R)1 + rP : rP;
-            const R d_w = (R)0.5 * geo(ax, kGeoW, cw[ax] + 2);
-            const R mloc[3] = {rho * sp[1 + ax_loc[0]][pc], rho * sp[1 + ax_loc[1]][pc], rho * sp[1 + ax_loc[2]][pc]};
+            const R d_w = (R)0.5 * geo(AX, kGeoW, wa + 2);
+            const R mloc[3] = {rho * sp[1 + AX][pc], rho * sp[1 + T1][pc], rho * sp[1 + T2][pc]};
             R G[5];
             wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, d.kind[side] == kIsothermal, (R)d.Tw[side],
                                  ph, G);
             F[0] = G[0];
+            F[1 + AX] = G[1];
+            F[1 + T1] = G[2];
+            F[1 + T2] = G[3];
             F[4] = G[4];
-            for (int k = 0; k < 3; ++k) F[1 + ax_loc[k]] = G[1 + k];
         } else {
             Side<R, 3> A, B;
-            const int pL = TL::pidx(cL[0] + 2, cL[1] + 2, cL[2] + 2), pR = TL::pidx(cR[0] + 2, cR[1] + 2, cR[2] + 2);
-            const int gL = TL::gidx(cL[0] + 1, cL[1] + 1, cL[2] + 1), gR = TL::gidx(cR[0] + 1, cR[1] + 1, cR[2] + 1);
-            // local primitive order: r, u_n, u_t1, u_t2, T
-            const int pmap[5] = {0, 1 + ax_loc[0], 1 + ax_loc[1], 1 + ax_loc[2], 4};
+            const int pL = TL::pidx(cL[0] + 2, cL[1] + 2, cL[2] + 2), pR = TL::pidx(f[0] + 2, f[1] + 2, f[2] + 2);
+            const int gL = TL::gidx(cL[0] + 1, cL[1] + 1, cL[2] + 1), gR = TL::gidx(f[0] + 1, f[1] + 1, f[2] + 1);
+            // local primitive order: r, u_n, u_t1, u_t2, T; local axes n, t1, t2
+            constexpr int pmap[5] = {0, 1 + AX, 1 + T1, 1 + T2, 4};
+            constexpr int amap[3] = {AX, T1, T2};
 #pragma unroll
             for (int p = 0; p < 5; ++p) {
                 A.v[p] = sp[pmap[p]][pL];
                 B.v[p] = sp[pmap[p]][pR];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    A.g[k][p] = sg[pmap[p]][ax_loc[k]][gL];
-                    B.g[k][p] = sg[pmap[p]][ax_loc[k]][gR];
+                    A.g[k][p] = sg[pmap[p]][amap[k]][gL];
+                    B.g[k][p] = sg[pmap[p]][amap[k]][gR];
                 }
             }
-            const R dL = (R)0.5 * geo(ax, kGeoW, cL[ax] + 2);
-            const R dR = (R)0.5 * geo(ax, kGeoW, cR[ax] + 2);
+            const R dL = (R)0.5 * geo(AX, kGeoW, cL[AX] + 2);
+            const R dR = (R)0.5 * geo(AX, kGeoW, f[AX] + 2);
             R fdir[3];
-            for (int k = 0; k < 3; ++k) fdir[k] = (d.force_pred && d.gaxis == ax_loc[k]) ? (R)1 : (R)0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fdir[k] = (d.force_pred && d.gaxis == amap[k]) ? (R)1 : (R)0;
             R G[5];
             face_flux<R, 3, DEV>(A, B, dL, dR, fdir, ph, G);
             F[0] = G[0];
+            F[1 + AX] = G[1];
+            F[1 + T1] = G[2];
+            F[1 + T2] = G[3];
             F[4] = G[4];
-            for (int k = 0; k < 3; ++k) F[1 + ax_loc[k]] = G[1 + k];
         }
-        if (ax == 0) {
+        if (AX == 0) {
             const int o = (f[2] * TY + f[1]) * (TX + 1) + f[0];
+#pragma unroll
             for (int k = 0; k < 5; ++k) sf0[k][o] = F[k] * area;
-        } else if (ax == 1) {
+        } else if (AX == 1) {
             const int o = (f[2] * (TY + 1) + f[1]) * TX + f[0];
+#pragma unroll
             for (int k = 0; k < 5; ++k) sf1[k][o] = F[k] * area;
         } else {
             const int o = (f[2] * TY + f[1]) * TX + f[0];
+#pragma unroll
             for (int k = 0; k < 5; ++k) sf2[k][o] = F[k] * area;
         }
+    };
+    for (int q = tid; q < TL::NF0 + TL::NF1 + TL::NF2; q += nthr) {
+        if (q < TL::NF0) face_axis(std::integral_constant<int, 0>{}, q);
+        else if (q < TL::NF0 + TL::NF1) face_axis(std::integral_constant<int, 1>{}, q - TL::NF0);
+        else face_axis(std::integral_constant<int, 2>{}, q - TL::NF0 - TL::NF1);
     }
     __syncthreads();
 
