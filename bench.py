@@ -31,11 +31,71 @@ TDEV = (0.5, -0.5, 0.0, 0.0)  # hot at x = 0
 GAXIS = 1
 BYTES_PER_CELL = {"f32": 4 * 4 * 2, "f64": 4 * 8 * 2}  # read + write of the 4 stored fields
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# Algorithmic flops per 2D cell-update (additions, multiplications and
+# divisions of one time step, per cell): two faces (428 FP32-deviation / 407
+# FP64-plain each, counted on the library's face function by
+# tests/test_flops_cpu.py) + Eq. 55 gradients 64 (4 primitives x 2 axes x 8)
+# + primitives 5 (4 plain) + area weighting 8 + update and buoyancy 23
+# + the FP32 stochastic rounding of 4 fields 24 (TwoSum, 6 each).
+FLOPS_PER_CELL = {"f32": 2 * 428 + 64 + 5 + 8 + 23 + 24, "f64": 2 * 407 + 64 + 4 + 8 + 23}
+CSRC = os.path.join(ROOT, "paper_2202_13449_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step2d_fp32_cavity256.json")
 
 
-def make_solver(rt, precision):
+def kernel_sources_sha256() -> str:
+    """Hash of the HIP sources, so stored counter data is used only while the
+    kernels are unchanged."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel
+    calibration); None when the kernels changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def make_solver(rt, precision, residual_every=100, mass_fix_every=1000):
     return rt.Solver(2, (N_CELLS_SIDE, N_CELLS_SIDE), (STRETCH, STRETCH), KIND, TDEV, GAXIS, Ra=RA, Pr=PR, Ma=MA,
-                     precision=precision, seed=1, noise_amp=1e-6, residual_every=100, mass_fix_every=1000)
+                     precision=precision, seed=1, noise_amp=1e-6, residual_every=residual_every,
+                     mass_fix_every=mass_fix_every)
+
+
+KERNEL_CHUNK = 2000
+
+
+def time_step_kernel(rt, torch, precision, steps, warmup):
+    """Average duration of one step-kernel launch: the same workload with the
+    reductions moved out of the way (Eq. 65 residual on one step in
+    KERNEL_CHUNK, no mass fix), timed with events on the solver's stream."""
+    s = make_solver(rt, precision, residual_every=KERNEL_CHUNK, mass_fix_every=-1)
+    s.step(max(warmup, KERNEL_CHUNK))
+    s.sync()
+    steps = max(KERNEL_CHUNK, steps - steps % KERNEL_CHUNK)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s.sync()
+    return e0.elapsed_time(e1) / steps, [s.info.tile_x, s.info.tile_y]
 
 
 def time_path(rt, torch, precision, steps, warmup):
@@ -270,16 +330,29 @@ def main():
                                "FP32 deviation storage, FP64 reductions",
                    "cells": cells, "residual_every": 100, "mass_fix_every": 1000},
     }
-    bpl = BYTES_PER_CELL["f32"] * cells  # algorithmic bytes per step-kernel launch
-    achieved = bpl / (ms32 * 1e-3) / 1e9
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    # Dominant kernel: the FP32 step kernel, one launch per step.  It is
+    # bound by vector ALU work (about 30 flop per algorithmic byte), so the
+    # roofline is the FP32 vector peak; the HBM fraction is reported beside it.
+    fpl = FLOPS_PER_CELL["f32"] * cells   # algorithmic flops per step-kernel launch
+    bpl = BYTES_PER_CELL["f32"] * cells   # algorithmic bytes per step-kernel launch
+    kms, ktile = time_step_kernel(rt, torch, rt.FP32_DEV, args.steps, args.warmup)
+    achieved = fpl / (kms * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
+                       "kernel": "k_step2d<float, deviation>", "kernel_us": kms * 1e3, "kernel_tile": ktile,
+                       "flops_per_cell": FLOPS_PER_CELL["f32"], "bytes_per_cell": BYTES_PER_CELL["f32"],
+                       "hbm_achieved_gbs": bpl / (kms * 1e-3) / 1e9,
+                       "hbm_frac": bpl / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out["nu_fp32"] = r32["nu"]
+    out["tile"] = [r32["solver"].info.tile_x, r32["solver"].info.tile_y]
     if not args.fp32_only:
         r64 = time_path(rt, torch, rt.FP64_PLAIN, args.steps, args.warmup)
         ms64 = r64["event_ms"] / args.steps
         out["fp64_plain"] = {"value": cells / (ms64 * 1e-3), "ms_per_step": ms64,
                              "hbm_gbs": BYTES_PER_CELL["f64"] * cells / (ms64 * 1e-3) / 1e9,
+                             "tflops": FLOPS_PER_CELL["f64"] * cells / (ms64 * 1e-3) / 1e12,
+                             "fp64_frac": FLOPS_PER_CELL["f64"] * cells / (ms64 * 1e-3) / 1e12
+                             / FP64_VECTOR_PEAK_TFLOPS,
                              "nu": r64["nu"]}
         out["nu_rel_diff_fp32_vs_fp64"] = {k: abs(r32["nu"][k] - r64["nu"][k]) / abs(r64["nu"][k])
                                            for k in r64["nu"]}

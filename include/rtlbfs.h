@@ -105,6 +105,10 @@ typedef struct {
     double nu, chi, beta_g;
     int tile;             /* 2D kernel tile: 0 -> autotuned at create (every shape timed on the
                              live state); 1..5 -> 32x8, 16x16, 64x4, 16x8, 8x8 cells */
+    int round_nearest;    /* FP32_DEV only. 0 (default): the state update u + du is rounded
+                             stochastically (unbiased; random bits from a hash of cell, field and a
+                             device step counter, reproducible); 1: round-to-nearest, which stalls
+                             increments below half an ulp near steady state */
 } rtlbfs_opts;
 
 typedef struct {

@@ -220,7 +220,7 @@ inline void pack_geometry(const Problem &p, int precision, std::vector<char> &by
 }
 
 // Everything of the kernel-side Domain except the device pointers.
-inline void fill_domain(const Problem &p, int precision, int force_pred, Domain &d) {
+inline void fill_domain(const Problem &p, int precision, int force_pred, int round_nearest, Domain &d) {
     std::memset(&d, 0, sizeof(d));
     d.dim = p.D;
     for (int a = 0; a < 3; ++a) {
@@ -234,6 +234,7 @@ inline void fill_domain(const Problem &p, int precision, int force_pred, Domain 
     }
     d.gaxis = p.bc.gravity_axis;
     d.force_pred = force_pred;
+    d.sround = (precision == RTLBFS_FP32_DEV && !round_nearest) ? 1 : 0;
     d.nu = p.nu;
     d.chi = p.chi;
     d.bg = p.bg;

@@ -25,20 +25,27 @@ using namespace rtlbfs::host;
 
 template <typename R, bool DEV, int TX, int TY, bool RES>
 __global__ void __launch_bounds__((tile2_threads<TX, TY>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_step2d(Domain d, const R *__restrict__ Uin,
-                                                                    R *__restrict__ Uout, double *__restrict__ parts) {
+                                                                    R *__restrict__ Uout, double *__restrict__ parts,
+                                                                    const uint32_t *__restrict__ ctr_in,
+                                                                    uint32_t *__restrict__ ctr_out) {
+    const uint32_t key = *ctr_in;  // step counter of the stochastic rounding
     const int ntx = (d.n[0] + TX - 1) / TX;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % ntx) * TX, j0 = (t / ntx) * TY;
-    tile_step_2d<R, DEV, TX, TY, RES>(d, i0, j0, Uin, Uout, parts + (int64_t)t * kPartials);
+    tile_step_2d<R, DEV, TX, TY, RES>(d, i0, j0, Uin, Uout, parts + (int64_t)t * kPartials, key);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
 __global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((amdgpu_waves_per_eu(4, 8))) k_step3d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
-                                                double *__restrict__ parts) {
+                                                double *__restrict__ parts, const uint32_t *__restrict__ ctr_in,
+                                                uint32_t *__restrict__ ctr_out) {
+    const uint32_t key = *ctr_in;
     const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     tile_step_3d<R, DEV, TX, TY, TZ, RES>(
         d, bx * TX, by * TY, bz * TZ, Uin, Uout,
-        parts + ((int64_t)(bz * gridDim.y + by) * gridDim.x + bx) * kPartials);
+        parts + ((int64_t)(bz * gridDim.y + by) * gridDim.x + bx) * kPartials, key);
+    if (bx == 0 && by == 0 && bz == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
 namespace {
@@ -127,6 +134,7 @@ struct rtlbfs_handle {
     double *int_out() { return red() + 16; }    // [16..19)
     double *m0() { return red() + 20; }         // [20]
     double *fix_out() { return red() + 24; }    // [24..27)
+    uint32_t *ctr() { return (uint32_t *)(red() + 28); }  // step counters of the two copies
 };
 
 namespace {
@@ -201,11 +209,12 @@ int read_stored(rtlbfs_t h, int k, std::vector<double> &out) {
 }
 
 template <typename R, bool DEV, int TX, int TY>
-hipError_t launch_step2d(const Domain &d, const R *Uin, R *Uout, double *parts, bool res, hipStream_t s) {
+hipError_t launch_step2d(const Domain &d, const R *Uin, R *Uout, double *parts, const uint32_t *ci, uint32_t *co,
+                         bool res, hipStream_t s) {
     const int nb = ((d.n[0] + TX - 1) / TX) * ((d.n[1] + TY - 1) / TY);
     constexpr int nt = tile2_threads<TX, TY>();
-    if (res) k_step2d<R, DEV, TX, TY, true><<<nb, nt, 0, s>>>(d, Uin, Uout, parts);
-    else k_step2d<R, DEV, TX, TY, false><<<nb, nt, 0, s>>>(d, Uin, Uout, parts);
+    if (res) k_step2d<R, DEV, TX, TY, true><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
+    else k_step2d<R, DEV, TX, TY, false><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
     return hipGetLastError();
 }
 
@@ -214,19 +223,21 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     const Domain &d = h->dom;
     const R *Uin = (const R *)h->U(src);
     R *Uout = (R *)h->U(src ^ 1);
+    const uint32_t *ci = h->ctr() + src;
+    uint32_t *co = h->ctr() + (src ^ 1);
     if (d.dim == 2) {
         switch (tile) {
-            case 0: return launch_step2d<R, DEV, 32, 8>(d, Uin, Uout, h->parts(), res, s);
-            case 1: return launch_step2d<R, DEV, 16, 16>(d, Uin, Uout, h->parts(), res, s);
-            case 2: return launch_step2d<R, DEV, 64, 4>(d, Uin, Uout, h->parts(), res, s);
-            case 3: return launch_step2d<R, DEV, 16, 8>(d, Uin, Uout, h->parts(), res, s);
-            default: return launch_step2d<R, DEV, 8, 8>(d, Uin, Uout, h->parts(), res, s);
+            case 0: return launch_step2d<R, DEV, 32, 8>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 1: return launch_step2d<R, DEV, 16, 16>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 2: return launch_step2d<R, DEV, 64, 4>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 3: return launch_step2d<R, DEV, 16, 8>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            default: return launch_step2d<R, DEV, 8, 8>(d, Uin, Uout, h->parts(), ci, co, res, s);
         }
     }
     dim3 grid((d.n[0] + kTX3 - 1) / kTX3, (d.n[1] + kTY3 - 1) / kTY3, (d.n[2] + kTZ3 - 1) / kTZ3);
     constexpr int nt = tile3_threads<kTX3, kTY3, kTZ3>();
-    if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
-    else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts());
+    if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
+    else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
     return hipGetLastError();
 }
 
@@ -400,7 +411,7 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
     h->L = P.L;
     const std::vector<double> &widths = P.widths;
     Domain &d = h->dom;
-    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, d);
+    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, d);
 
     // Workspace.
     if (workspace) {
@@ -433,6 +444,8 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
         for (int a = 0; a < D; ++a) d.geo[a] = h->ws + h->lay.off_geo + goff[a];
         hipError_t e = hipMemcpy(wdev, widths.data(), widths.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(h->ws + h->lay.off_geo, geo.data(), geo.size(), hipMemcpyHostToDevice);
+        const uint32_t zero2[2] = {0u, 0u};
+        if (e == hipSuccess) e = hipMemcpy(h->ctr(), zero2, sizeof(zero2), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             int r2 = hip_fail(h, e, "upload geometry");
             rtlbfs_destroy(h);

@@ -32,14 +32,17 @@ constexpr int kBRedBlocks = 512;
 template <typename R, bool DEV, bool RES>
 __global__ void __launch_bounds__((tile2_threads<kBTX, kBTY>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_batch_step2d(const Domain *__restrict__ doms,
                                                                               const int2 *__restrict__ work, int cur,
-                                                                              double *__restrict__ parts) {
+                                                                              double *__restrict__ parts,
+                                                                              uint32_t *__restrict__ ctr) {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int2 w = work[b];
     const Domain &d = doms[w.x];
     const int ntx = (d.n[0] + kBTX - 1) / kBTX;
     const int i0 = (w.y % ntx) * kBTX, j0 = (w.y / ntx) * kBTY;
+    const uint32_t key = ctr[cur];  // step counter of the stochastic rounding
     tile_step_2d<R, DEV, kBTX, kBTY, RES>(d, i0, j0, (const R *)d.U[cur], (R *)d.U[cur ^ 1],
-                                          parts + (int64_t)b * kPartials);
+                                          parts + (int64_t)b * kPartials, key);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[cur ^ 1] = key + 1u;
 }
 
 // Per-tile integrals {sum r dV, sum theta dV, sum dV} of the deviation state.
@@ -113,6 +116,7 @@ struct rtlbfs_batch_handle {
     double *int_out() { return res_out() + (size_t)count * 8; }                  // count * 3
     double *m0() { return int_out() + (size_t)count * 3; }                        // count
     double *nu_out() { return m0() + count; }                                     // 8
+    uint32_t *ctr() { return (uint32_t *)(nu_out() + 8); }                        // 2 step counters
 };
 
 namespace {
@@ -154,7 +158,7 @@ BatchLayout batch_layout(int count, const rtlbfs_mesh *meshes, int precision) {
     l.off_parts = off;
     off += align256(sizeof(double) * (size_t)std::max(l.nwork, kBRedBlocks) * 8);
     l.off_red = off;
-    off += align256(sizeof(double) * ((size_t)count * 12 + 16));
+    off += align256(sizeof(double) * ((size_t)count * 12 + 24));
     l.bytes = off;
     return l;
 }
@@ -175,10 +179,10 @@ template <typename R, bool DEV>
 hipError_t batch_launch(rtlbfs_batch_t h, bool res, hipStream_t s) {
     if (res)
         k_batch_step2d<R, DEV, true><<<h->nwork, tile2_threads<kBTX, kBTY>(), 0, s>>>(h->doms_dev(), h->work_dev(),
-                                                                                    h->cur, h->parts());
+                                                                                    h->cur, h->parts(), h->ctr());
     else
         k_batch_step2d<R, DEV, false><<<h->nwork, tile2_threads<kBTX, kBTY>(), 0, s>>>(h->doms_dev(), h->work_dev(),
-                                                                                     h->cur, h->parts());
+                                                                                     h->cur, h->parts(), h->ctr());
     return hipGetLastError();
 }
 
@@ -327,7 +331,7 @@ int rtlbfs_batch_create(int count, const rtlbfs_mesh *meshes, const double *Ra, 
     for (int m = 0; m < count; ++m) {
         const Problem &P = h->prob[m];
         Domain &d = h->dom[m];
-        fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, d);
+        fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, d);
         double *wdev = (double *)(h->ws + L.off_member_w[m]);
         d.w[0] = wdev;
         d.w[1] = wdev + P.mesh.n[0];
@@ -369,6 +373,8 @@ int rtlbfs_batch_create(int count, const rtlbfs_mesh *meshes, const double *Ra, 
         hipMemcpy(h->begin_dev(), h->begin.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->m0(), m0.data(), sizeof(double) * count, hipMemcpyHostToDevice) != hipSuccess)
         return bail(RTLBFS_EDEVICE);
+    const uint32_t zero2[2] = {0u, 0u};
+    if (hipMemcpy(h->ctr(), zero2, sizeof(zero2), hipMemcpyHostToDevice) != hipSuccess) return bail(RTLBFS_EDEVICE);
     *out = h;
     return RTLBFS_OK;
 }

@@ -33,6 +33,7 @@ struct Domain {
     double Tw[6];
     int gaxis;        // buoyancy along +gaxis, -1 none
     int force_pred;   // 1: buoyancy also in the predicted momentum
+    int sround;       // 1: stochastic rounding of the FP32 state update
     double nu, chi, bg, dtl, dt, tau_f, tau_g;
     const double *w[3];  // cell widths per axis (device, FP64; diagnostics)
     const void *geo[3];  // per-axis geometry records in the kernel precision (see kGeo*)
@@ -265,6 +266,41 @@ __host__ __device__ inline void wall_flux(R rP, const R (&m)[D], R eP, R sgn, R 
     for (int q = 1; q < D; ++q) out[1 + q] = sgn * ph.nu * m[q] * inv_d;
     out[D + 1] = iso ? -sgn * ph.chi * (rho * Tw - eP) * inv_d : (R)0;
 }
+
+// ------------------------------------------------------ stochastic rounding --
+
+// 32-bit integer finaliser of MurmurHash3 (Appleby) applied to a combined
+// (cell, field, step) key: the counter-based random source of the stochastic
+// rounding below.
+__device__ inline uint32_t sr_hash(uint32_t a, uint32_t b) {
+    uint32_t x = a * 0x9E3779B1u ^ (b * 0x85EBCA77u + 0x27D4EB2Fu);
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
+}
+
+// a + b rounded stochastically to float: the exact sum s + e (TwoSum) is
+// rounded to the neighbour of s on the side of e with probability |e|/gap, so
+// the stored state is unbiased even when the increments are far below half an
+// ulp (plain round-to-nearest would stall the slow modes near steady state).
+__device__ inline float sr_add(float a, float b, uint32_t rnd) {
+    const float s = a + b;
+    const float bp = s - a;
+    const float e = (a - (s - bp)) + (b - bp);  // s + e == a + b exactly (TwoSum)
+    // neighbour of s on the side of e: one ulp up in magnitude when e has the
+    // sign of s, one down otherwise (the bit pattern of a float is monotone in
+    // its magnitude); s == 0 only when |a + b| is below the smallest float.
+    const bool away = (e > 0.0f) == (s > 0.0f);
+    const float t = __uint_as_float(__float_as_uint(s) + (away ? 1u : 0xFFFFFFFFu));
+    const float u = (float)(rnd >> 8) * 5.9604644775390625e-8f;  // [0, 1), 24 random bits
+    const bool up = e != 0.0f && s != 0.0f && fabsf(u * (t - s)) < fabsf(e);  // P(up) = |e| / |t - s|
+    return up ? t : s;
+}
+
+__device__ inline double sr_add(double a, double b, uint32_t) { return a + b; }
 
 __device__ inline int wrap(int i, int n) {
     i %= n;

@@ -37,7 +37,7 @@ __device__ inline int xcd_tile(int b, int nb) {
 
 template <typename R, bool DEV, int TX, int TY, bool RES>
 __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, const R *__restrict__ Uin,
-                                             R *__restrict__ Uout, double *__restrict__ part) {
+                                             R *__restrict__ Uout, double *__restrict__ part, uint32_t step_key) {
     constexpr int PX = TX + 4, PY = TY + 4;  // primitives with a 2-cell halo
     constexpr int GX = TX + 2, GY = TY + 2;  // gradients with a 1-cell halo
     __shared__ R sp[4][PY][PX];
@@ -231,16 +231,27 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
         if (gi >= nx || gj >= ny) continue;
         const int64_t c = (int64_t)gj * nx + gi;
         const R dt_dV = dtR * sgx[kGeoInvW][lc + 2] * sgy[kGeoInvW][lr + 2];
-        R Un[4];
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            const R div = (sfx[f][lr][lc] - sfx[f][lr][lc + 1]) + (sfy[f][lr][lc] - sfy[f][lr + 1][lc]);
-            Un[f] = sc[f][lr][lc] + dt_dV * div;
-        }
         const R rP = sp[0][lr + 2][lc + 2];
         const R rhoP = DEV ? (R)1 + rP : rP;
         const R TP = sp[3][lr + 2][lc + 2];
-        if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+        R Un[4];
+        if (sizeof(R) == 4 && d.sround) {
+            // increments first, then one stochastically rounded addition per field
+            R inc[4];
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                inc[f] = dt_dV * ((sfx[f][lr][lc] - sfx[f][lr][lc + 1]) + (sfy[f][lr][lc] - sfy[f][lr + 1][lc]));
+            if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) Un[f] = sr_add(sc[f][lr][lc], inc[f], sr_hash((uint32_t)c, step_key * 4u + f));
+        } else {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const R div = (sfx[f][lr][lc] - sfx[f][lr][lc + 1]) + (sfy[f][lr][lc] - sfy[f][lr + 1][lc]);
+                Un[f] = sc[f][lr][lc] + dt_dV * div;
+            }
+            if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+        }
 #pragma unroll
         for (int f = 0; f < 4; ++f) Uout[f * N + c] = Un[f];
         if (RES) {

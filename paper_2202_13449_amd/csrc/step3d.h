@@ -32,7 +32,7 @@ constexpr int tile3_threads() {
 
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
 __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, int k0, const R *__restrict__ Uin,
-                                             R *__restrict__ Uout, double *__restrict__ part) {
+                                             R *__restrict__ Uout, double *__restrict__ part, uint32_t step_key) {
     using TL = Tile3<TX, TY, TZ>;
     constexpr int NPRIM = 5;
     __shared__ R sp[NPRIM][TL::NP];
@@ -228,18 +228,29 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         const int o0 = (z * TY + y) * (TX + 1) + x;
         const int o1 = (z * (TY + 1) + y) * TX + x;
         const int o2 = (z * TY + y) * TX + x;
-        R Un[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const R div = (sf0[k][o0] - sf0[k][o0 + 1]) + (sf1[k][o1] - sf1[k][o1 + TX]) +
-                          (sf2[k][o2] - sf2[k][o2 + TX * TY]);
-            Un[k] = Uin[k * N + c] + dt_dV * div;
-        }
         const int pc = TL::pidx(x + 2, y + 2, z + 2);
         const R rP = sp[0][pc];
         const R rhoP = DEV ? (R)1 + rP : rP;
         const R TP = sp[4][pc];
-        if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+        R Un[5];
+        if (sizeof(R) == 4 && d.sround) {
+            R inc[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                inc[k] = dt_dV * ((sf0[k][o0] - sf0[k][o0 + 1]) + (sf1[k][o1] - sf1[k][o1 + TX]) +
+                                  (sf2[k][o2] - sf2[k][o2 + TX * TY]));
+            if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) Un[k] = sr_add(Uin[k * N + c], inc[k], sr_hash((uint32_t)c, step_key * 5u + k));
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const R div = (sf0[k][o0] - sf0[k][o0 + 1]) + (sf1[k][o1] - sf1[k][o1 + TX]) +
+                              (sf2[k][o2] - sf2[k][o2 + TX * TY]);
+                Un[k] = Uin[k * N + c] + dt_dV * div;
+            }
+            if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+        }
 #pragma unroll
         for (int k = 0; k < 5; ++k) Uout[k * N + c] = Un[k];
         if (RES) {

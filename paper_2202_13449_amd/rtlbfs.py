@@ -46,6 +46,7 @@ class Opts(C.Structure):
         ("chi", C.c_double),
         ("beta_g", C.c_double),
         ("tile", C.c_int),
+        ("round_nearest", C.c_int),
     ]
 
 

@@ -1,0 +1,52 @@
+// Host-side operation count of the interior-face flux of the GPU library:
+// the face function is instantiated with a number type that counts every
+// addition, subtraction, multiplication and division.  Test infrastructure.
+#include <cstdio>
+
+#include "rtlbfs_device.h"
+
+struct CountedReal {
+    double v;
+    static long adds, muls, divs;
+    CountedReal(double x = 0) : v(x) {}
+    friend CountedReal operator+(CountedReal a, CountedReal b) { ++adds; return CountedReal(a.v + b.v); }
+    friend CountedReal operator-(CountedReal a, CountedReal b) { ++adds; return CountedReal(a.v - b.v); }
+    friend CountedReal operator*(CountedReal a, CountedReal b) { ++muls; return CountedReal(a.v * b.v); }
+    friend CountedReal operator/(CountedReal a, CountedReal b) { ++divs; return CountedReal(a.v / b.v); }
+    CountedReal operator-() const { return CountedReal(-v); }
+    CountedReal &operator+=(CountedReal b) { ++adds; v += b.v; return *this; }
+    CountedReal &operator-=(CountedReal b) { ++adds; v -= b.v; return *this; }
+    explicit operator double() const { return v; }
+};
+long CountedReal::adds = 0, CountedReal::muls = 0, CountedReal::divs = 0;
+
+template <int D, bool DEV>
+void count(const char *name) {
+    using R = CountedReal;
+    rtlbfs::Side<R, D> L, Rt;
+    for (int p = 0; p < D + 2; ++p) {
+        L.v[p] = 1.0 + 0.1 * p;
+        Rt.v[p] = 1.0 + 0.2 * p;
+        for (int k = 0; k < D; ++k) {
+            L.g[k][p] = 0.01;
+            Rt.g[k][p] = 0.02;
+        }
+    }
+    rtlbfs::Phys<R> ph;
+    ph.nu = 0.1; ph.chi = 0.1; ph.dtl = 1.0; ph.tau_f = 0.8; ph.tau_g = 0.9; ph.bg = 1e-3;
+    ph.h = 1.0; ph.inv2h = 0.5; ph.invh2 = 1.0; ph.inv4h2 = 0.25;
+    R fdir[D];
+    for (int k = 0; k < D; ++k) fdir[k] = k == 1 ? 1.0 : 0.0;
+    R out[D + 2];
+    R::adds = R::muls = R::divs = 0;
+    rtlbfs::face_flux<R, D, DEV>(L, Rt, R(0.5), R(0.5), fdir, ph, out);
+    std::printf("%s %ld %ld %ld\n", name, R::adds, R::muls, R::divs);
+}
+
+int main() {
+    count<2, false>("2d_plain");
+    count<2, true>("2d_dev");
+    count<3, false>("3d_plain");
+    count<3, true>("3d_dev");
+    return 0;
+}

@@ -261,3 +261,32 @@ def test_fp32_deviation_nusselt_at_steady_state():
     a, b = s.nusselt(), o.nusselt()
     for k in ("hot_avg", "cold_avg", "volume", "hot_max", "cold_max"):
         assert abs(a[k] - b[k]) <= 1e-4 * abs(b[k]), (k, a[k], b[k])
+
+
+def test_fp32_stochastic_rounding_removes_the_steady_state_bias():
+    """Near steady state the FP32 increments fall below half an ulp of the
+    stored deviation variables; round-to-nearest then stalls the slow modes
+    and biases the converged Nusselt number, while stochastic rounding of the
+    update is unbiased.  128^2 tanh cavity at Ra = 1e5 run until the FP64
+    residual is below 1e-8: FP32 (stochastic) Nusselt numbers within 1e-4 of
+    FP64, and closer than round-to-nearest."""
+    args = (2, (128, 128), (1.5, 1.5), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"])
+    kw = dict(Ra=1e5, noise_amp=1e-6, seed=1, residual_every=1000)
+    ref = rt.Solver(*args, precision=rt.FP64_PLAIN, **kw)
+    n = 0
+    while n < 2_000_000:
+        ref.step(20000)
+        n += 20000
+        if max(ref.residual()) < 1e-8:
+            break
+    assert max(ref.residual()) < 1e-8
+    sr = rt.Solver(*args, precision=rt.FP32_DEV, **kw)
+    rn = rt.Solver(*args, precision=rt.FP32_DEV, round_nearest=1, **kw)
+    sr.step(n)
+    rn.step(n)
+    a, b, c = ref.nusselt(), sr.nusselt(), rn.nusselt()
+    for k in ("hot_avg", "cold_avg", "volume"):
+        e_sr = abs(b[k] - a[k]) / abs(a[k])
+        e_rn = abs(c[k] - a[k]) / abs(a[k])
+        assert e_sr <= 1e-4, (k, e_sr)
+        assert e_sr < e_rn, (k, e_sr, e_rn)
