@@ -287,31 +287,59 @@ hipError_t enqueue_mass_fix(rtlbfs_t h, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Autotuner: time every 2D tile shape on the live state (each trial writes
-// only the spare copy, so the state is unchanged) and keep the fastest.
+// Autotuner: time every 2D tile shape on the live state and keep the
+// fastest.  Each trial writes only the spare copy, so the state is unchanged.
+// The launches of one tile are replayed from a captured graph (direct
+// launches of a few-microsecond kernel would time the host's launch rate),
+// and the tiles are timed in interleaved rounds, keeping each tile's best
+// round, so that clock ramps and neighbours on the device bias no tile.
 int autotune_tile(rtlbfs_t h) {
     if (h->mesh.dim != 2) return RTLBFS_OK;
-    hipEvent_t e0, e1;
-    HIP_TRY(h, hipEventCreate(&e0));
-    HIP_TRY(h, hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_t = 0;
-    for (int t = 0; t < kNumTiles2; ++t) {
-        for (int k = 0; k < 3; ++k) HIP_TRY(h, launch_any(h, t, h->cur, false, h->stream));
-        HIP_TRY(h, hipEventRecord(e0, h->stream));
-        for (int k = 0; k < 20; ++k) HIP_TRY(h, launch_any(h, t, h->cur, false, h->stream));
-        HIP_TRY(h, hipEventRecord(e1, h->stream));
-        HIP_TRY(h, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-        h->tune_ms[t] = ms / 20.0f;
-        if (ms < best) {
-            best = ms;
-            best_t = t;
+    constexpr int kLaunches = 32, kRounds = 4;
+    hipGraphExec_t ge[kNumTiles2] = {};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = RTLBFS_OK;
+    float best_ms[kNumTiles2];
+    for (int t = 0; t < kNumTiles2; ++t) best_ms[t] = 1e30f;
+    auto cleanup = [&]() {
+        for (int t = 0; t < kNumTiles2; ++t)
+            if (ge[t]) (void)hipGraphExecDestroy(ge[t]);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int t = 0; t < kNumTiles2 && e == hipSuccess; ++t) {
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) break;
+        hipError_t el = hipSuccess;
+        for (int k = 0; k < kLaunches && el == hipSuccess; ++k) el = launch_any(h, t, h->cur, false, h->cap_stream);
+        e = hipStreamEndCapture(h->cap_stream, &g);
+        if (el != hipSuccess) e = el;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge[t], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+    }
+    for (int t = 0; t < kNumTiles2 && e == hipSuccess; ++t) e = hipGraphLaunch(ge[t], h->stream);  // warm-up
+    for (int r = 0; r < kRounds && e == hipSuccess; ++r) {
+        for (int t = 0; t < kNumTiles2 && e == hipSuccess; ++t) {
+            e = hipEventRecord(e0, h->stream);
+            if (e == hipSuccess) e = hipGraphLaunch(ge[t], h->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) best_ms[t] = std::min(best_ms[t], ms / kLaunches);
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) rc = hip_fail(h, e, "tile autotuning");
+    cleanup();
+    if (rc != RTLBFS_OK) return rc;
+    int best_t = 0;
+    for (int t = 0; t < kNumTiles2; ++t) {
+        h->tune_ms[t] = best_ms[t];
+        if (best_ms[t] < best_ms[best_t]) best_t = t;
+    }
     h->tile = best_t;
     return RTLBFS_OK;
 }
