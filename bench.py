@@ -179,21 +179,37 @@ def timed(torch, solver, steps):
     return e0.elapsed_time(e1) / steps
 
 
+RB_TOTAL_STEPS, RB_AVG_STEPS, RB_SAMPLE_EVERY = 200_000, 50_000, 1_000
+
+
 def rb_bench(rt, torch, steps, warmup):
     """1024 x 512 Rayleigh-Benard box, periodic in x, Ra = 1e8 on H = 512,
-    conduction profile plus 1e-3 seeded noise, FP32 deviation storage: a long
-    unsteady run (stability) and its throughput."""
+    conduction profile plus 1e-3 seeded noise, FP32 deviation storage: the
+    throughput over `steps`, then the run continued to 200,000 steps with the
+    wall and volume Nusselt numbers averaged over the last 50,000 (sampled
+    every 1,000 steps), max |u| and finiteness at the end."""
     s = rt.Solver(2, (1024, 512), (0, 0), (0, 0, 1, 1), (0, 0, 0.5, -0.5), 1, Ra=1e8, Pr=0.71, Ma=MA,
                   precision=rt.FP32_DEV, init=rt.INIT_CONDUCTION, seed=3, noise_amp=1e-3)
     s.step(warmup)
     ms = timed(torch, s, steps)
+    done = warmup + steps
+    samples = []
+    while done < RB_TOTAL_STEPS:
+        k = min(RB_SAMPLE_EVERY - done % RB_SAMPLE_EVERY, RB_TOTAL_STEPS - done)
+        s.step(k)
+        done += k
+        if done % RB_SAMPLE_EVERY == 0 and done > RB_TOTAL_STEPS - RB_AVG_STEPS:
+            samples.append(s.nusselt())
+    s.sync()
     u, v = s.field(1), s.field(2)
     umax = float(np.sqrt(u * u + v * v).max())
     cells = 1024 * 512
-    nu = s.nusselt()
-    return {"workload": "rb1024x512 Ra=1e8 FP32", "cells": cells, "steps": steps + warmup, "ms_per_step": ms,
+    avg = {k: float(np.mean([x[k] for x in samples])) for k in ("hot_avg", "cold_avg", "volume")} if samples else {}
+    return {"workload": "rb1024x512 Ra=1e8 FP32", "cells": cells, "steps_timed": steps, "ms_per_step": ms,
             "value": cells / (ms * 1e-3), "hbm_gbs": BYTES_PER_CELL["f32"] * cells / (ms * 1e-3) / 1e9,
-            "finite": bool(np.isfinite(umax)), "umax": umax, "nu": nu,
+            "total_steps": done, "finite": bool(np.isfinite(umax)), "umax": umax,
+            "pass": bool(np.isfinite(umax) and umax < 0.3),
+            "nu_time_avg_last_50k": avg, "nu_samples": len(samples), "nu_final": s.nusselt(),
             "tile": [s.info.tile_x, s.info.tile_y]}
 
 
@@ -208,6 +224,79 @@ def cube_bench(rt, torch, steps, warmup):
         ms = timed(torch, s, steps)
         out[name] = {"ms_per_step": ms, "value": 192 ** 3 / (ms * 1e-3),
                      "hbm_gbs": bpc * 192 ** 3 / (ms * 1e-3) / 1e9, "nu": s.nusselt()}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+TABLE5 = {1e5: {"u_max": 0.141, "z": 0.147, "w_max": 0.245, "x": 0.936, "Nu_m": 4.613, "Nu_o": 4.337},
+          1e6: {"u_max": 0.0812, "z": 0.138, "w_max": 0.257, "x": 0.963, "Nu_m": 8.882, "Nu_o": 8.643}}
+
+
+def _peak(xc, f):
+    """Maximum of samples f at nodes xc by the parabola through the largest
+    sample and its two neighbours: (position, value)."""
+    k = int(np.argmax(f))
+    k = min(max(k, 1), len(f) - 2)
+    x0, x1, x2 = xc[k - 1:k + 2]
+    y0, y1, y2 = f[k - 1:k + 2]
+    A = np.array([[x0 * x0, x0, 1.0], [x1 * x1, x1, 1.0], [x2 * x2, x2, 1.0]])
+    a, b, c = np.linalg.solve(A, [y0, y1, y2])
+    if a >= 0:
+        return float(xc[int(np.argmax(f))]), float(f.max())
+    xm = -b / (2 * a)
+    return float(xm), float(a * xm * xm + b * xm + c)
+
+
+def cube_table5_bench(rt, torch, steps, warmup, n=80, chunk=20_000, max_steps=800_000, tol=2e-5):
+    """The 3D cubic cavity of the paper's Sec. 4.4 on its 80^3 tanh mesh (phi =
+    1.8), Ra = 1e5 and 1e6, FP32 deviation storage, run until the hot-wall
+    Nusselt number changes by less than tol (relative) over a chunk.  Reported
+    against the printed 'Present' values: u_max / V_c on the vertical centre
+    line (x = y = L/2) and its height, w_max / V_c on the horizontal centre
+    line (y = z = L/2) and its position, Nu_m on the line x = L, y = L/2
+    (Eq. 75) and the hot-wall average Nu_o (Eq. 76)."""
+    out = {"workload": f"cube{n} tanh1.8 Table 5", "cases": {}}
+    x, L = rt.mesh_nodes(n, 1.8)
+    xc = 0.5 * (x[1:] + x[:-1]) / L
+    w_first = (x[1] - x[0])
+    h = n // 2
+    for Ra in (1e5, 1e6):
+        s = rt.Solver(3, (n, n, n), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=Ra,
+                      Pr=0.71, Ma=MA, precision=rt.FP32_DEV, seed=1, noise_amp=1e-6)
+        t0 = time.perf_counter()
+        done, prev, nu = 0, None, None
+        while done < max_steps:
+            s.step(chunk)
+            done += chunk
+            nu = s.nusselt()
+            if prev is not None and abs(nu["hot_avg"] - prev) < tol * abs(nu["hot_avg"]):
+                break
+            prev = nu["hot_avg"]
+        el = time.perf_counter() - t0
+        sh = (n, n, n)  # (z, y, x) with x fastest
+        u = s.field(1).reshape(sh)
+        w = s.field(3).reshape(sh)
+        T = s.field(4).reshape(sh)
+        Vc = MA
+        # centre lines: the mid-planes fall between cells h - 1 and h (symmetric mesh)
+        u_line = u[:, h - 1:h + 1, h - 1:h + 1].mean(axis=(1, 2)) / Vc
+        w_line = w[h - 1:h + 1, h - 1:h + 1, :].mean(axis=(0, 1)) / Vc
+        zu, umax = _peak(xc, u_line)
+        xw, wmax = _peak(xc, w_line)
+        # Nu_m: hot wall at x = L (T = 1), one-sided gradient over the half cell
+        Twall = 1.0
+        dTdx = (Twall - T[:, h - 1:h + 1, n - 1].mean(axis=1)) / (0.5 * w_first)
+        dz = np.diff(x) / L
+        Nu_m = float(np.sum(dTdx * L * dz))
+        out["cases"][f"{Ra:g}"] = {
+            "steps": done, "seconds": el, "nu": nu,
+            "u_max": umax, "z": zu, "w_max": wmax, "x": xw, "Nu_m": Nu_m, "Nu_o": nu["hot_avg"],
+            "paper_present": TABLE5[Ra],
+            "rel_diff": {k: abs(v - TABLE5[Ra][k]) / TABLE5[Ra][k]
+                         for k, v in (("u_max", umax), ("w_max", wmax), ("Nu_m", Nu_m), ("Nu_o", nu["hot_avg"]))},
+        }
+        print(json.dumps({f"Ra={Ra:g}": out["cases"][f"{Ra:g}"]}), flush=True)
         del s
         torch.cuda.empty_cache()
     return out
@@ -277,9 +366,10 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
-    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256"],
+    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
-                         "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt")
+                         "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
+                         "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -306,7 +396,8 @@ def main():
         print(json.dumps(batch_bench(rt, torch, args.steps, args.warmup)), flush=True)
         return
     if args.workload != "cavity256":
-        fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench}[args.workload]
+        fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,
+              "cube80": cube_table5_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE

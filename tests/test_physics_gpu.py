@@ -1,0 +1,73 @@
+"""Steady-state physics of the GPU path against values the paper prints.
+
+Sec. 4.4, Table 5: natural convection in a cubic cavity on an 80^3 tanh mesh
+(phi = 1.8), Pr = 0.71, V_c = 0.1, hot wall at x = L, gravity along -z.  The
+FP32 deviation path is run to steady state at Ra = 1e5 and compared with the
+'Present' column (tests/golden/table5_cubic.txt): the centre-line velocity
+maxima and their positions, the mid-plane Nusselt number Nu_m (Eq. 75) and
+the hot-wall average Nu_o (Eq. 76).  The reproduction agrees to about 1e-3;
+the bounds below leave room for the printed three-digit rounding.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2202_13449_amd as rt
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table5_cubic.txt")
+
+
+def table5():
+    rows = {}
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [float(t) for t in line.split()]
+            rows[v[0]] = dict(u_max=v[1], z=v[2], w_max=v[3], x=v[4], Nu_m=v[5], Nu_o=v[6])
+    return rows
+
+
+def peak(xc, f):
+    """Position and value of the maximum of samples f at nodes xc (parabola
+    through the largest sample and its neighbours)."""
+    k = min(max(int(np.argmax(f)), 1), len(f) - 2)
+    A = np.array([[xc[j] ** 2, xc[j], 1.0] for j in (k - 1, k, k + 1)])
+    a, b, c = np.linalg.solve(A, f[k - 1:k + 2])
+    xm = -b / (2 * a)
+    return xm, a * xm * xm + b * xm + c
+
+
+def test_cubic_cavity_ra1e5_matches_table5():
+    n, Ra, Vc = 80, 1e5, 0.1
+    ref = table5()[Ra]
+    s = rt.Solver(3, (n, n, n), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=Ra, Pr=0.71,
+                  Ma=Vc, precision=rt.FP32_DEV, seed=1, noise_amp=1e-6)
+    prev = None
+    for _ in range(40):  # at most 800,000 steps; converges near 400,000
+        s.step(20_000)
+        nu = s.nusselt()["hot_avg"]
+        if prev is not None and abs(nu - prev) < 2e-5 * nu:
+            break
+        prev = nu
+    x, L = rt.mesh_nodes(n, 1.8)
+    xc = 0.5 * (x[1:] + x[:-1]) / L
+    h = n // 2
+    u = s.field(1).reshape(n, n, n)  # (z, y, x)
+    w = s.field(3).reshape(n, n, n)
+    T = s.field(4).reshape(n, n, n)
+    zu, umax = peak(xc, u[:, h - 1:h + 1, h - 1:h + 1].mean(axis=(1, 2)) / Vc)
+    xw, wmax = peak(xc, w[h - 1:h + 1, h - 1:h + 1, :].mean(axis=(0, 1)) / Vc)
+    dTdx = (1.0 - T[:, h - 1:h + 1, n - 1].mean(axis=1)) / (0.5 * (x[n] - x[n - 1]))
+    Nu_m = float(np.sum(dTdx * L * np.diff(x) / L))
+    nus = s.nusselt()
+    assert abs(umax - ref["u_max"]) < 0.005 * ref["u_max"]
+    assert abs(wmax - ref["w_max"]) < 0.005 * ref["w_max"]
+    assert abs(zu - ref["z"]) < 0.005 and abs(xw - ref["x"]) < 0.005
+    assert abs(Nu_m - ref["Nu_m"]) < 0.002 * ref["Nu_m"]
+    assert abs(nus["hot_avg"] - ref["Nu_o"]) < 0.002 * ref["Nu_o"]
+    # energy balance at steady state: hot and cold walls carry the same heat
+    assert abs(nus["hot_avg"] - nus["cold_avg"]) < 1e-4 * nus["hot_avg"]
