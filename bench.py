@@ -31,7 +31,11 @@ TDEV = (0.5, -0.5, 0.0, 0.0)  # hot at x = 0
 GAXIS = 1
 BYTES_PER_CELL = {"f32": 4 * 4 * 2, "f64": 4 * 8 * 2}  # read + write of the 4 stored fields
 HBM_PEAK_GBS = 8000.0
+# Published MI355X vector peaks.  FP32 157.3 TFLOP/s = 256 CU x 4 SIMD x 16
+# lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz; without packed FP32
+# instructions (which the build disables) the FP32 ceiling is half, 78.6.
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_PEAK_TFLOPS = 78.6
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # Algorithmic flops per 2D cell-update (additions, multiplications and
 # divisions of one time step, per cell): two faces (428 FP32-deviation / 407
@@ -57,10 +61,11 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel
-    calibration); None when the kernels changed since it was taken."""
+def measured_traffic(tile):
+    """HBM bytes per launch of the dominant kernel (tile shape `tile`) from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its
+    copy-kernel calibration); None when the kernels changed since it was
+    taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -68,23 +73,26 @@ def measured_traffic():
         return None
     if t.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch_by_tile", {}).get(f"{tile[0]}x{tile[1]}")
 
 
-def make_solver(rt, precision, residual_every=100, mass_fix_every=1000):
+TILES_2D = {(32, 8): 1, (16, 16): 2, (64, 4): 3, (16, 8): 4, (8, 8): 5}  # opts.tile of each 2D tile shape
+
+
+def make_solver(rt, precision, residual_every=100, mass_fix_every=1000, tile=0):
     return rt.Solver(2, (N_CELLS_SIDE, N_CELLS_SIDE), (STRETCH, STRETCH), KIND, TDEV, GAXIS, Ra=RA, Pr=PR, Ma=MA,
                      precision=precision, seed=1, noise_amp=1e-6, residual_every=residual_every,
-                     mass_fix_every=mass_fix_every)
+                     mass_fix_every=mass_fix_every, tile=tile)
 
 
 KERNEL_CHUNK = 2000
 
 
-def time_step_kernel(rt, torch, precision, steps, warmup):
-    """Average duration of one step-kernel launch: the same workload with the
-    reductions moved out of the way (Eq. 65 residual on one step in
+def time_step_kernel(rt, torch, precision, steps, warmup, tile):
+    """Average duration of one step-kernel launch: the same workload and tile
+    with the reductions moved out of the way (Eq. 65 residual on one step in
     KERNEL_CHUNK, no mass fix), timed with events on the solver's stream."""
-    s = make_solver(rt, precision, residual_every=KERNEL_CHUNK, mass_fix_every=-1)
+    s = make_solver(rt, precision, residual_every=KERNEL_CHUNK, mass_fix_every=-1, tile=tile)
     s.step(max(warmup, KERNEL_CHUNK))
     s.sync()
     steps = max(KERNEL_CHUNK, steps - steps % KERNEL_CHUNK)
@@ -426,10 +434,13 @@ def main():
     # roofline is the FP32 vector peak; the HBM fraction is reported beside it.
     fpl = FLOPS_PER_CELL["f32"] * cells   # algorithmic flops per step-kernel launch
     bpl = BYTES_PER_CELL["f32"] * cells   # algorithmic bytes per step-kernel launch
-    kms, ktile = time_step_kernel(rt, torch, rt.FP32_DEV, args.steps, args.warmup)
+    tile32 = (r32["solver"].info.tile_x, r32["solver"].info.tile_y)
+    kms, ktile = time_step_kernel(rt, torch, rt.FP32_DEV, args.steps, args.warmup, TILES_2D[tile32])
     achieved = fpl / (kms * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
+                       "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(ktile),
+                       "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS,
+                       "frac_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS,
                        "kernel": "k_step2d<float, deviation>", "kernel_us": kms * 1e3, "kernel_tile": ktile,
                        "flops_per_cell": FLOPS_PER_CELL["f32"], "bytes_per_cell": BYTES_PER_CELL["f32"],
                        "hbm_achieved_gbs": bpl / (kms * 1e-3) / 1e9,

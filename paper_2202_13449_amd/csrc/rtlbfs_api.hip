@@ -41,11 +41,13 @@ __global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((
                                                 double *__restrict__ parts, const uint32_t *__restrict__ ctr_in,
                                                 uint32_t *__restrict__ ctr_out) {
     const uint32_t key = *ctr_in;
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    tile_step_3d<R, DEV, TX, TY, TZ, RES>(
-        d, bx * TX, by * TY, bz * TZ, Uin, Uout,
-        parts + ((int64_t)(bz * gridDim.y + by) * gridDim.x + bx) * kPartials, key);
-    if (bx == 0 && by == 0 && bz == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
+    // tiles x-fastest; each XCD takes a contiguous band of them (see xcd_tile)
+    const int ntx = (d.n[0] + TX - 1) / TX, nty = (d.n[1] + TY - 1) / TY;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
+    tile_step_3d<R, DEV, TX, TY, TZ, RES>(d, bx * TX, by * TY, bz * TZ, Uin, Uout, parts + (int64_t)t * kPartials,
+                                          key);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
 namespace {
@@ -234,7 +236,7 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
             default: return launch_step2d<R, DEV, 8, 8>(d, Uin, Uout, h->parts(), ci, co, res, s);
         }
     }
-    dim3 grid((d.n[0] + kTX3 - 1) / kTX3, (d.n[1] + kTY3 - 1) / kTY3, (d.n[2] + kTZ3 - 1) / kTZ3);
+    const int grid = ((d.n[0] + kTX3 - 1) / kTX3) * ((d.n[1] + kTY3 - 1) / kTY3) * ((d.n[2] + kTZ3 - 1) / kTZ3);
     constexpr int nt = tile3_threads<kTX3, kTY3, kTZ3>();
     if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
     else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
