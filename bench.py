@@ -49,15 +49,22 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step2d_fp32_cavity256.j
 
 
 def kernel_sources_sha256() -> str:
-    """Hash of the HIP sources, so stored counter data is used only while the
-    kernels are unchanged."""
+    """Hash of what defines the 2D step kernel (its device headers, its
+    __global__ wrapper and the build flags), so stored counter data is used
+    only while that kernel is unchanged."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in ("rtlbfs_device.h", "step2d.h"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(CSRC, "rtlbfs_api.hip")) as f:
+        api = f.read()
+    m = re.search(r"template <typename R, bool DEV, int TX, int TY, bool RES>\n__global__.*?\n}\n", api, re.S)
+    h.update(b"k_step2d\0" + (m.group(0).encode() if m else b""))
+    with open(os.path.join(ROOT, "paper_2202_13449_amd", "build.py"), "rb") as f:
+        h.update(b"build.py\0" + f.read())
     return h.hexdigest()
 
 
