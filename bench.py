@@ -317,6 +317,36 @@ def cube_table5_bench(rt, torch, steps, warmup, n=80, chunk=20_000, max_steps=80
     return out
 
 
+def hill_bench(rt, torch, steps, warmup, sizes=(80, 120, 160, 200, 240)):
+    """Sec. 4.1 accuracy study (Fig. 7): the Gaussian hill advected and
+    diffused on the periodic [0, 2L]^2 box (L = N/2 cells, dtl = 0.5, Delta t
+    = 1, chi = 0.1 so Fo_dx = 0.1, Pe = 10, nu = chi), E_2 of Eq. 68 against
+    Eq. 67 at Fo = 0.005 on the paper's five meshes, and the fitted order."""
+    out = {"workload": "Gaussian hill, Sec. 4.1", "sizes": list(sizes)}
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import inputs  # seeded inputs and the closed form of Eq. 67
+
+    for name, prec in (("fp64_plain", rt.FP64_PLAIN), ("fp32_dev", rt.FP32_DEV), ("fp64_dev", rt.FP64_DEV)):
+        errs = []
+        for N in sizes:
+            L = N / 2.0
+            chi = 0.1
+            u0 = 10.0 * chi / L
+            s = rt.Solver(2, (N, N), (0, 0), (0, 0, 0, 0), (0, 0, 0, 0), -1, phys_given=1, nu=chi, chi=chi,
+                          beta_g=0.0, dtl=0.5, dt=1.0, precision=prec)
+            xc = np.arange(N) + 0.5
+            u = np.zeros((2, N * N))
+            u[0] = u0
+            s.set_state(np.ones(N * N), u, inputs.gaussian_hill(xc, xc, L, 0.0, chi, u0).reshape(-1))
+            n = int(round(0.005 * L * L / chi))
+            s.step(n)
+            Ta = inputs.gaussian_hill(xc, xc, L, float(n), chi, u0).reshape(-1)
+            errs.append(float(np.sqrt(np.mean((s.field(3) - Ta) ** 2))))
+        order = -float(np.polyfit(np.log(sizes), np.log(errs), 1)[0])
+        out[name] = {"E2": errs, "order": order}
+    return out
+
+
 def steady_bench(rt, torch, steps, warmup, tol=1e-8, max_steps=4_000_000, chunk=20000):
     """The 256^2 cavity run to steady state: FP64 plain until both Eq. 65
     ratios are below tol, then FP32 deviation for the same number of steps;
@@ -381,10 +411,11 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
-    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80"],
+    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
                          "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
-                         "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5")
+                         "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5; "
+                         "hill: the Gaussian-hill convergence study of Sec. 4.1")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -412,7 +443,7 @@ def main():
         return
     if args.workload != "cavity256":
         fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,
-              "cube80": cube_table5_bench}[args.workload]
+              "cube80": cube_table5_bench, "hill": hill_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE

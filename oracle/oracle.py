@@ -17,6 +17,7 @@ from .build import LIB, build
 
 PERIODIC, WALL_ISOTHERMAL, WALL_ADIABATIC = 0, 1, 2
 INIT_REST, INIT_CONDUCTION = 0, 1
+RTLBFS, TLBFS = 0, 1  # interior-face flux: Sec. 3.2 (Eqs. 46-48, 57-59) or Sec. 2.2 (Eqs. 29-40)
 
 
 class _Cfg(C.Structure):
@@ -37,6 +38,7 @@ class _Cfg(C.Structure):
         ("init", C.c_int),
         ("seed", C.c_uint64),
         ("noise_amp", C.c_double),
+        ("method", C.c_int),
     ]
 
 
@@ -106,6 +108,7 @@ class OracleConfig:
     init: int = INIT_REST
     seed: int = 0
     noise_amp: float = 0.0
+    method: int = RTLBFS
 
     def to_c(self) -> _Cfg:
         c = _Cfg()
@@ -124,6 +127,7 @@ class OracleConfig:
         c.init = self.init
         c.seed = self.seed
         c.noise_amp = self.noise_amp
+        c.method = self.method
         return c
 
 

@@ -178,24 +178,19 @@ static double d2(const nodefield *f, int a, int b, double h)
     return (nf(f, pp) - nf(f, pm) - nf(f, mp) + nf(f, mm)) / (4.0 * h * h);
 }
 
-void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
-                   const double *primR, const double *gradR, double dL, double dR,
-                   double *flux, double *pred)
+/* Primitives at every node of the face lattice by Eq. 29.  Node (a, b, c)
+ * sits at x_S + h (a n + b t1 + c t2); relative to the left centre that is
+ * (dL + a h) along the face normal and (b h, c h) along the tangential axes;
+ * relative to the right centre the normal part is (a h - dR).  val[p] is
+ * indexed by the local offsets. */
+static void reconstruct_nodes(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
+                              const double *primR, const double *gradR, double dL, double dR,
+                              nodefield *val)
 {
     const int D = cfg->dim;
     const int NP = D + 2;
-    const int dev = cfg->deviation;
-    const double h = cfg->dtl; /* lattice spacing c*dtl with c = 1 */
-    const double dtl = cfg->dtl;
-    const double tau_f = 0.5 + cfg->nu / (CS2 * dtl); /* Eq. 9 */
-    const double tau_g = 0.5 + cfg->chi / (CS2 * dtl); /* Eq. 10 */
-
-    /* Step 1: primitives at every lattice node by Eq. 29.  Node position
-     * relative to the left centre: (dL + a h) along the face normal and
-     * (b h, c h) along the tangential axes; relative to the right centre the
-     * normal part is (a h - dR). */
-    nodefield val[5];
-    memset(val, 0, sizeof(val));
+    const double h = cfg->dtl;
+    memset(val, 0, sizeof(nodefield) * 5);
     for (int a = -1; a <= 1; ++a)
         for (int b = -1; b <= 1; ++b)
             for (int c = -1; c <= 1; ++c) {
@@ -228,6 +223,28 @@ void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const doub
                     val[p].v[a + 1][b + 1][c + 1] = v;
                 }
             }
+}
+
+static void tlbfs_face_flux(const orc_cfg *cfg, int axis, const nodefield *val, double *flux, double *pred);
+
+void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
+                   const double *primR, const double *gradR, double dL, double dR,
+                   double *flux, double *pred)
+{
+    const int D = cfg->dim;
+    const int dev = cfg->deviation;
+    const double h = cfg->dtl; /* lattice spacing c*dtl with c = 1 */
+    const double dtl = cfg->dtl;
+    const double tau_f = 0.5 + cfg->nu / (CS2 * dtl); /* Eq. 9 */
+    const double tau_g = 0.5 + cfg->chi / (CS2 * dtl); /* Eq. 10 */
+
+    /* Step 1: primitives at the lattice nodes (Eq. 29). */
+    nodefield val[5];
+    reconstruct_nodes(cfg, axis, primL, gradL, primR, gradR, dL, dR, val);
+    if (cfg->method == 1) {
+        tlbfs_face_flux(cfg, axis, val, flux, pred);
+        return;
+    }
 
     /* Step 2: node values of the conserved quantities and of the moments that
      * Eqs. 46-48 differentiate.  Index the node fields by the GLOBAL axis:
@@ -357,12 +374,120 @@ void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const doub
     }
 }
 
+/* TLBFS interface flux (Sec. 2.2), in the paper's order:
+ *   (a) primitives at x_S - e_i dt by Eq. 29 (the lattice nodes above: node
+ *       offset (a, b, c) = -e_i in the face frame), and f_i^eq, g_i^eq there
+ *       by Eqs. 3-4;
+ *   (b) the predicted rho*, rho* u*, rho* c_p T* at x_S by Eqs. 30-32 (the
+ *       buoyancy enters the predicted momentum as dt F at the face centre,
+ *       the same reading as for RTLBFS), and f_i^eq, g_i^eq at x_S from them;
+ *   (c) the fluxes of Eqs. 38-40 along the face normal.
+ * D2Q9 / D3Q19 velocities and weights of Eqs. 5-6 (c = 1), c_p = 1.  The
+ * computation is done in absolute variables; with deviation storage the
+ * node values are converted first and the fluxes afterwards (the r flux is the
+ * rho flux, the theta flux is Q - T0 P, and the constant pressure c_s^2 is
+ * left out of the momentum flux). */
+static void tlbfs_face_flux(const orc_cfg *cfg, int axis, const nodefield *val, double *flux, double *pred)
+{
+    const int D = cfg->dim;
+    const int dev = cfg->deviation;
+    const double dtl = cfg->dtl;
+    const double tau_f = 0.5 + cfg->nu / (CS2 * dtl); /* Eq. 9 */
+    const double tau_g = 0.5 + cfg->chi / (CS2 * dtl); /* Eq. 10 */
+    int tmap[3];
+    {
+        int t = 1;
+        tmap[0] = axis;
+        for (int ax = 0; ax < D; ++ax)
+            if (ax != axis) tmap[t++] = ax;
+        if (D == 2) tmap[2] = 2;
+    }
+
+    /* (a) the discrete velocities with their weights and the equilibria at
+     * the nodes they stream from */
+    int Q = 0;
+    double e[19][3], w[19], fb[19], gb[19];
+    double rho_c = 0.0, T_c = 0.0; /* face-centre node (e_i = 0), for the force */
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                if (!node_in_lattice(D, a, b, c)) continue;
+                int loc[3] = {a, b, c};
+                double eg[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < 3; ++k) eg[tmap[k]] = -(double)loc[k]; /* e_i = -offset */
+                int nz = abs(a) + abs(b) + abs(c);
+                double wi = D == 2 ? (nz == 0 ? 4.0 / 9.0 : nz == 1 ? 1.0 / 9.0 : 1.0 / 36.0)
+                                   : (nz == 0 ? 1.0 / 3.0 : nz == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+                double r0 = val[0].v[a + 1][b + 1][c + 1];
+                double rho = dev ? 1.0 + r0 : r0;
+                double u[3] = {0.0, 0.0, 0.0};
+                for (int ax = 0; ax < D; ++ax) u[ax] = val[1 + ax].v[a + 1][b + 1][c + 1];
+                double T = val[D + 1].v[a + 1][b + 1][c + 1] + (dev ? TREF : 0.0);
+                double eu = 0.0, uu = 0.0;
+                for (int ax = 0; ax < D; ++ax) {
+                    eu += eg[ax] * u[ax];
+                    uu += u[ax] * u[ax];
+                }
+                for (int ax = 0; ax < 3; ++ax) e[Q][ax] = eg[ax];
+                w[Q] = wi;
+                fb[Q] = wi * rho * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2)); /* Eq. 3 */
+                gb[Q] = wi * rho * T * (1.0 + eu / CS2);                                           /* Eq. 4 */
+                if (nz == 0) {
+                    rho_c = rho;
+                    T_c = T;
+                }
+                ++Q;
+            }
+
+    /* (b) Eqs. 30-32 */
+    double rhos = 0.0, ms[3] = {0.0, 0.0, 0.0}, Es = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        rhos += fb[i];
+        for (int ax = 0; ax < D; ++ax) ms[ax] += e[i][ax] * fb[i];
+        Es += gb[i];
+    }
+    if (cfg->gravity_axis >= 0 && cfg->force_in_predictor)
+        ms[cfg->gravity_axis] += dtl * cfg->beta_g * rho_c * (T_c - TREF); /* Eq. 64 at the face centre */
+    double us[3] = {0.0, 0.0, 0.0};
+    for (int ax = 0; ax < D; ++ax) us[ax] = ms[ax] / rhos;
+    double Ts = Es / rhos;
+    double fs[19], gs[19];
+    for (int i = 0; i < Q; ++i) {
+        double eu = 0.0, uu = 0.0;
+        for (int ax = 0; ax < D; ++ax) {
+            eu += e[i][ax] * us[ax];
+            uu += us[ax] * us[ax];
+        }
+        fs[i] = w[i] * rhos * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+        gs[i] = w[i] * rhos * Ts * (1.0 + eu / CS2);
+    }
+
+    /* (c) Eqs. 38-40 along n = axis */
+    const int n = axis;
+    double P = 0.0, Pi[3] = {0.0, 0.0, 0.0}, Qn = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        P += e[i][n] * fs[i];
+        for (int ax = 0; ax < D; ++ax)
+            Pi[ax] += e[i][ax] * e[i][n] * (fs[i] + (0.5 - tau_f) * (fs[i] - fb[i]));
+        Qn += e[i][n] * (gs[i] + (0.5 - tau_g) * (gs[i] - gb[i]));
+    }
+    flux[0] = P;
+    for (int ax = 0; ax < D; ++ax) flux[1 + ax] = Pi[ax] - ((dev && ax == n) ? CS2 : 0.0);
+    flux[D + 1] = dev ? Qn - TREF * P : Qn;
+    if (pred) {
+        pred[0] = dev ? rhos - 1.0 : rhos;
+        for (int ax = 0; ax < D; ++ax) pred[1 + ax] = ms[ax];
+        pred[D + 1] = dev ? Es - TREF * rhos : Es;
+    }
+}
+
 /* ----------------------------------------------------------------- setup -- */
 
 int orc_create(const orc_cfg *cfg, orc_state **out)
 {
     if (!cfg || !out) return -1;
     if (cfg->dim != 2 && cfg->dim != 3) return -1;
+    if (cfg->method != 0 && cfg->method != 1) return -1;
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
     if (!s) return -2;
     s->c = *cfg;

@@ -42,6 +42,8 @@ typedef struct {
     int init;               /* ORC_INIT_REST or ORC_INIT_CONDUCTION */
     uint64_t seed;          /* SplitMix64 seed for the initial temperature noise */
     double noise_amp;       /* T' += noise_amp * U(-1, 1) per cell */
+    int method;             /* interior-face flux: 0 RTLBFS (Sec. 3.2, Eqs. 46-48, 57-59);
+                               1 TLBFS (Sec. 2.2, Eqs. 29-40) */
 } orc_cfg;
 
 typedef struct orc_state orc_state;
@@ -85,12 +87,14 @@ void orc_integrals(const orc_state *s, double *out);
 /* Derived relaxation times: out = {tau_f, tau_g}. */
 void orc_taus(const orc_state *s, double *out);
 
-/* Single interior-face flux, for pinning the face arithmetic in isolation.
+/* Single interior-face flux (RTLBFS or TLBFS by cfg->method), for pinning the
+ * face arithmetic in isolation.
  * primL/primR hold D+2 primitives in the storage convention of cfg->deviation
  * (rho or r, u_a, T or T'); gradL/gradR hold their gradients [p*3 + a].
  * dL/dR: distances from the left/right cell centre to the face.  flux: D+2
  * values per unit area along +axis.  pred (optional): rho*, m*_a, e* (or
- * r*, m*, theta*) at the face centre. */
+ * r*, m*, theta*) at the face centre.  With deviation storage the momentum
+ * flux omits the constant pressure c_s^2 (it cancels on every cell). */
 void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
                    const double *primR, const double *gradR, double dL, double dR,
                    double *flux, double *pred);

@@ -71,3 +71,63 @@ def test_cubic_cavity_ra1e5_matches_table5():
     assert abs(nus["hot_avg"] - ref["Nu_o"]) < 0.002 * ref["Nu_o"]
     # energy balance at steady state: hot and cold walls carry the same heat
     assert abs(nus["hot_avg"] - nus["cold_avg"]) < 1e-4 * nus["hot_avg"]
+
+
+HILL_SIZES = (80, 120, 160, 200, 240)
+
+
+def hill_error(N, precision):
+    """Sec. 4.1 set-up on the GPU: periodic [0, 2L]^2 with L = N/2 cells,
+    dtl = 0.5, Delta t = 1, Fo_dx = 0.1 (chi = 0.1), Pe = 10, nu = chi;
+    E_2 of Eq. 68 against Eq. 67 at Fo = 0.005."""
+    import inputs
+
+    L = N / 2.0
+    chi = 0.1
+    u0 = 10.0 * chi / L
+    s = rt.Solver(2, (N, N), (0, 0), (0, 0, 0, 0), (0, 0, 0, 0), -1, phys_given=1, nu=chi, chi=chi, beta_g=0.0,
+                  dtl=0.5, dt=1.0, precision=precision)
+    xc = np.arange(N) + 0.5
+    u = np.zeros((2, N * N))
+    u[0] = u0
+    s.set_state(np.ones(N * N), u, inputs.gaussian_hill(xc, xc, L, 0.0, chi, u0).reshape(-1))
+    steps = int(round(0.005 * L * L / chi))
+    s.step(steps)
+    Ta = inputs.gaussian_hill(xc, xc, L, float(steps), chi, u0).reshape(-1)
+    return float(np.sqrt(np.mean((s.field(3) - Ta) ** 2)))
+
+
+def test_gaussian_hill_convergence_order():
+    """Fig. 7: second-order convergence over the paper's five meshes, FP64
+    plain and FP32 deviation storage (the FP32 rounding floor stays far below
+    the discretisation error at these sizes)."""
+    for prec in (rt.FP64_PLAIN, rt.FP32_DEV):
+        errs = np.array([hill_error(N, prec) for N in HILL_SIZES])
+        order = -np.polyfit(np.log(HILL_SIZES), np.log(errs), 1)[0]
+        assert 1.85 <= order <= 2.15, (prec, errs, order)
+        assert np.all(np.diff(errs) < 0)
+    e64 = np.array([hill_error(N, rt.FP64_PLAIN) for N in (80, 240)])
+    e32 = np.array([hill_error(N, rt.FP32_DEV) for N in (80, 240)])
+    assert np.all(np.abs(e32 - e64) < 0.01 * e64), (e32, e64)
+
+
+def test_gaussian_hill_error_matches_the_oracle():
+    """The E_2 of the GPU FP64 path at 80^2 equals the oracle's (same method,
+    rounding-order differences only)."""
+    import inputs
+    from oracle import Oracle, OracleConfig
+
+    N, chi = 80, 0.1
+    L = N / 2.0
+    u0 = 10.0 * chi / L
+    o = Oracle(OracleConfig(n=(N, N), bc=(0,) * 6, gravity_axis=-1, nu=chi, chi=chi, dtl=0.5, dt=1.0))
+    xc, _ = o.axis(0)
+    u = np.zeros((2, N * N))
+    u[0] = u0
+    o.set_prim(np.ones(N * N), u, inputs.gaussian_hill(xc, xc, L, 0.0, chi, u0).reshape(-1))
+    steps = int(round(0.005 * L * L / chi))
+    o.step(steps)
+    Ta = inputs.gaussian_hill(xc, xc, L, float(steps), chi, u0).reshape(-1)
+    e_orc = float(np.sqrt(np.mean((o.prim(3) - Ta) ** 2)))
+    e_gpu = hill_error(N, rt.FP64_PLAIN)
+    assert abs(e_gpu - e_orc) <= 1e-9 * e_orc, (e_gpu, e_orc)
