@@ -321,19 +321,23 @@ def hill_bench(rt, torch, steps, warmup, sizes=(80, 120, 160, 200, 240)):
     """Sec. 4.1 accuracy study (Fig. 7): the Gaussian hill advected and
     diffused on the periodic [0, 2L]^2 box (L = N/2 cells, dtl = 0.5, Delta t
     = 1, chi = 0.1 so Fo_dx = 0.1, Pe = 10, nu = chi), E_2 of Eq. 68 against
-    Eq. 67 at Fo = 0.005 on the paper's five meshes, and the fitted order."""
+    Eq. 67 at Fo = 0.005 on the paper's five meshes, and the fitted order,
+    for RTLBFS and TLBFS (Fig. 7 compares the two)."""
     out = {"workload": "Gaussian hill, Sec. 4.1", "sizes": list(sizes)}
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import inputs  # seeded inputs and the closed form of Eq. 67
 
-    for name, prec in (("fp64_plain", rt.FP64_PLAIN), ("fp32_dev", rt.FP32_DEV), ("fp64_dev", rt.FP64_DEV)):
+    for name, prec, method in (("fp64_plain", rt.FP64_PLAIN, rt.METHOD_RTLBFS), ("fp32_dev", rt.FP32_DEV, rt.METHOD_RTLBFS),
+                               ("fp64_dev", rt.FP64_DEV, rt.METHOD_RTLBFS),
+                               ("tlbfs_fp64_plain", rt.FP64_PLAIN, rt.METHOD_TLBFS),
+                               ("tlbfs_fp32_dev", rt.FP32_DEV, rt.METHOD_TLBFS)):
         errs = []
         for N in sizes:
             L = N / 2.0
             chi = 0.1
             u0 = 10.0 * chi / L
             s = rt.Solver(2, (N, N), (0, 0), (0, 0, 0, 0), (0, 0, 0, 0), -1, phys_given=1, nu=chi, chi=chi,
-                          beta_g=0.0, dtl=0.5, dt=1.0, precision=prec)
+                          beta_g=0.0, dtl=0.5, dt=1.0, precision=prec, method=method)
             xc = np.arange(N) + 0.5
             u = np.zeros((2, N * N))
             u[0] = u0
@@ -344,6 +348,40 @@ def hill_bench(rt, torch, steps, warmup, sizes=(80, 120, 160, 200, 240)):
             errs.append(float(np.sqrt(np.mean((s.field(3) - Ta) ** 2))))
         order = -float(np.polyfit(np.log(sizes), np.log(errs), 1)[0])
         out[name] = {"E2": errs, "order": order}
+    return out
+
+
+def methods_bench(rt, torch, steps, warmup):
+    """Cost of the two interior-face fluxes on the same workloads (the paper's
+    Table 6 compares RTLBFS with TLBFS by CPU time): the 256^2 tanh cavity in
+    FP32 deviation and FP64 plain storage, and the 192^3 tanh cube in FP32,
+    each timed as whole graph-replayed steps with the tile fixed to the one
+    the autotuner picks for RTLBFS."""
+    out = {"workload": "RTLBFS vs TLBFS step cost"}
+    for name, prec in (("cavity256_fp32", rt.FP32_DEV), ("cavity256_fp64", rt.FP64_PLAIN)):
+        res = {}
+        tile = 0
+        for mname, method in (("rtlbfs", rt.METHOD_RTLBFS), ("tlbfs", rt.METHOD_TLBFS)):
+            s = rt.Solver(2, (N_CELLS_SIDE, N_CELLS_SIDE), (STRETCH, STRETCH), KIND, TDEV, GAXIS, Ra=RA, Pr=PR,
+                          Ma=MA, precision=prec, seed=1, noise_amp=1e-6, residual_every=KERNEL_CHUNK,
+                          mass_fix_every=-1, tile=tile, method=method)
+            tile = TILES_2D[(s.info.tile_x, s.info.tile_y)]
+            s.step(max(warmup, KERNEL_CHUNK))
+            n = max(KERNEL_CHUNK, steps - steps % KERNEL_CHUNK)
+            res[mname] = {"us_per_step": timed(torch, s, n) * 1e3, "tile": [s.info.tile_x, s.info.tile_y]}
+            del s
+        res["rtlbfs_over_tlbfs"] = res["rtlbfs"]["us_per_step"] / res["tlbfs"]["us_per_step"]
+        out[name] = res
+    res = {}
+    for mname, method in (("rtlbfs", rt.METHOD_RTLBFS), ("tlbfs", rt.METHOD_TLBFS)):
+        s = rt.Solver(3, (192, 192, 192), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=1e6,
+                      Pr=0.71, Ma=MA, precision=rt.FP32_DEV, seed=1, noise_amp=1e-6, method=method)
+        s.step(20)
+        res[mname] = {"ms_per_step": timed(torch, s, 200)}
+        del s
+        torch.cuda.empty_cache()
+    res["rtlbfs_over_tlbfs"] = res["rtlbfs"]["ms_per_step"] / res["tlbfs"]["ms_per_step"]
+    out["cube192_fp32"] = res
     return out
 
 
@@ -411,11 +449,11 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
-    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill"],
+    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
                          "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
                          "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5; "
-                         "hill: the Gaussian-hill convergence study of Sec. 4.1")
+                         "hill: the Gaussian-hill convergence study of Sec. 4.1; methods: RTLBFS vs TLBFS step cost")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -443,7 +481,7 @@ def main():
         return
     if args.workload != "cavity256":
         fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,
-              "cube80": cube_table5_bench, "hill": hill_bench}[args.workload]
+              "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE

@@ -62,6 +62,10 @@ extern "C" {
 #define RTLBFS_FP32_DEV 1   /* r = rho - 1, rho u, theta = rho c_p (T - T0) in float */
 #define RTLBFS_FP64_DEV 2   /* the deviation storage in double */
 
+/* Interior-face flux (opts.method). */
+#define RTLBFS_METHOD_RTLBFS 0 /* Sec. 3.2: finite-difference predictor of Eqs. 46-48, fluxes Eqs. 57-59 */
+#define RTLBFS_METHOD_TLBFS 1  /* Sec. 2.2: equilibria on the local lattice, Eqs. 29-40 */
+
 /* Initial state. */
 #define RTLBFS_INIT_REST 0       /* rho = 1, u = 0, T' = 0 (+ noise) */
 #define RTLBFS_INIT_CONDUCTION 1 /* linear T' between the isothermal walls (+ noise) */
@@ -109,6 +113,8 @@ typedef struct {
                              stochastically (unbiased; random bits from a hash of cell, field and a
                              device step counter, reproducible); 1: round-to-nearest, which stalls
                              increments below half an ulp near steady state */
+    int method;           /* RTLBFS_METHOD_RTLBFS (default) or RTLBFS_METHOD_TLBFS: the interior-face
+                             flux; wall faces, gradients, update and diagnostics are shared */
 } rtlbfs_opts;
 
 typedef struct {

@@ -23,7 +23,7 @@ using namespace rtlbfs::host;
 
 // ----------------------------------------------------------------- kernels --
 
-template <typename R, bool DEV, int TX, int TY, bool RES>
+template <typename R, bool DEV, int TX, int TY, bool RES, bool TL>
 __global__ void __launch_bounds__((tile2_threads<TX, TY>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_step2d(Domain d, const R *__restrict__ Uin,
                                                                     R *__restrict__ Uout, double *__restrict__ parts,
                                                                     const uint32_t *__restrict__ ctr_in,
@@ -32,11 +32,11 @@ __global__ void __launch_bounds__((tile2_threads<TX, TY>())) __attribute__((amdg
     const int ntx = (d.n[0] + TX - 1) / TX;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % ntx) * TX, j0 = (t / ntx) * TY;
-    tile_step_2d<R, DEV, TX, TY, RES>(d, i0, j0, Uin, Uout, parts + (int64_t)t * kPartials, key);
+    tile_step_2d<R, DEV, TX, TY, RES, TL>(d, i0, j0, Uin, Uout, parts + (int64_t)t * kPartials, key);
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
-template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
+template <typename R, bool DEV, int TX, int TY, int TZ, bool RES, bool TL>
 __global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((amdgpu_waves_per_eu(4, 8))) k_step3d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
                                                 double *__restrict__ parts, const uint32_t *__restrict__ ctr_in,
                                                 uint32_t *__restrict__ ctr_out) {
@@ -45,8 +45,8 @@ __global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((
     const int ntx = (d.n[0] + TX - 1) / TX, nty = (d.n[1] + TY - 1) / TY;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
-    tile_step_3d<R, DEV, TX, TY, TZ, RES>(d, bx * TX, by * TY, bz * TZ, Uin, Uout, parts + (int64_t)t * kPartials,
-                                          key);
+    tile_step_3d<R, DEV, TX, TY, TZ, RES, TL>(d, bx * TX, by * TY, bz * TZ, Uin, Uout,
+                                              parts + (int64_t)t * kPartials, key);
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
@@ -210,17 +210,17 @@ int read_stored(rtlbfs_t h, int k, std::vector<double> &out) {
     return RTLBFS_OK;
 }
 
-template <typename R, bool DEV, int TX, int TY>
+template <typename R, bool DEV, int TX, int TY, bool TL>
 hipError_t launch_step2d(const Domain &d, const R *Uin, R *Uout, double *parts, const uint32_t *ci, uint32_t *co,
                          bool res, hipStream_t s) {
     const int nb = ((d.n[0] + TX - 1) / TX) * ((d.n[1] + TY - 1) / TY);
     constexpr int nt = tile2_threads<TX, TY>();
-    if (res) k_step2d<R, DEV, TX, TY, true><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
-    else k_step2d<R, DEV, TX, TY, false><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
+    if (res) k_step2d<R, DEV, TX, TY, true, TL><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
+    else k_step2d<R, DEV, TX, TY, false, TL><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
     return hipGetLastError();
 }
 
-template <typename R, bool DEV>
+template <typename R, bool DEV, bool TL>
 hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     const Domain &d = h->dom;
     const R *Uin = (const R *)h->U(src);
@@ -229,26 +229,33 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     uint32_t *co = h->ctr() + (src ^ 1);
     if (d.dim == 2) {
         switch (tile) {
-            case 0: return launch_step2d<R, DEV, 32, 8>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            case 1: return launch_step2d<R, DEV, 16, 16>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            case 2: return launch_step2d<R, DEV, 64, 4>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            case 3: return launch_step2d<R, DEV, 16, 8>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            default: return launch_step2d<R, DEV, 8, 8>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 0: return launch_step2d<R, DEV, 32, 8, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 1: return launch_step2d<R, DEV, 16, 16, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 2: return launch_step2d<R, DEV, 64, 4, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 3: return launch_step2d<R, DEV, 16, 8, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            default: return launch_step2d<R, DEV, 8, 8, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
         }
     }
     const int grid = ((d.n[0] + kTX3 - 1) / kTX3) * ((d.n[1] + kTY3 - 1) / kTY3) * ((d.n[2] + kTZ3 - 1) / kTZ3);
     constexpr int nt = tile3_threads<kTX3, kTY3, kTZ3>();
-    if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
-    else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
+    if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
+    else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
     return hipGetLastError();
 }
 
 // One step kernel from copy `src` into the other copy (no state change on the host side).
 hipError_t launch_any(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
+    const bool tl = h->opts.method == RTLBFS_METHOD_TLBFS;
     switch (h->opts.precision) {
-        case RTLBFS_FP64_PLAIN: return launch_step<double, false>(h, tile, src, res, s);
-        case RTLBFS_FP64_DEV: return launch_step<double, true>(h, tile, src, res, s);
-        default: return launch_step<float, true>(h, tile, src, res, s);
+        case RTLBFS_FP64_PLAIN:
+            return tl ? launch_step<double, false, true>(h, tile, src, res, s)
+                      : launch_step<double, false, false>(h, tile, src, res, s);
+        case RTLBFS_FP64_DEV:
+            return tl ? launch_step<double, true, true>(h, tile, src, res, s)
+                      : launch_step<double, true, false>(h, tile, src, res, s);
+        default:
+            return tl ? launch_step<float, true, true>(h, tile, src, res, s)
+                      : launch_step<float, true, false>(h, tile, src, res, s);
     }
 }
 

@@ -29,7 +29,7 @@ namespace {
 constexpr int kBTX = 32, kBTY = 8;  // batch tile
 constexpr int kBRedBlocks = 512;
 
-template <typename R, bool DEV, bool RES>
+template <typename R, bool DEV, bool RES, bool TL>
 __global__ void __launch_bounds__((tile2_threads<kBTX, kBTY>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_batch_step2d(const Domain *__restrict__ doms,
                                                                               const int2 *__restrict__ work, int cur,
                                                                               double *__restrict__ parts,
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__((tile2_threads<kBTX, kBTY>())) __attribute__((
     const int ntx = (d.n[0] + kBTX - 1) / kBTX;
     const int i0 = (w.y % ntx) * kBTX, j0 = (w.y / ntx) * kBTY;
     const uint32_t key = ctr[cur];  // step counter of the stochastic rounding
-    tile_step_2d<R, DEV, kBTX, kBTY, RES>(d, i0, j0, (const R *)d.U[cur], (R *)d.U[cur ^ 1],
+    tile_step_2d<R, DEV, kBTX, kBTY, RES, TL>(d, i0, j0, (const R *)d.U[cur], (R *)d.U[cur ^ 1],
                                           parts + (int64_t)b * kPartials, key);
     if (blockIdx.x == 0 && threadIdx.x == 0) ctr[cur ^ 1] = key + 1u;
 }
@@ -175,23 +175,30 @@ int bfail(rtlbfs_batch_t h, int code, const std::string &msg) {
                                                                     hipGetErrorString(_e));  \
     } while (0)
 
-template <typename R, bool DEV>
+template <typename R, bool DEV, bool TL>
 hipError_t batch_launch(rtlbfs_batch_t h, bool res, hipStream_t s) {
     if (res)
-        k_batch_step2d<R, DEV, true><<<h->nwork, tile2_threads<kBTX, kBTY>(), 0, s>>>(h->doms_dev(), h->work_dev(),
-                                                                                    h->cur, h->parts(), h->ctr());
+        k_batch_step2d<R, DEV, true, TL><<<h->nwork, tile2_threads<kBTX, kBTY>(), 0, s>>>(
+            h->doms_dev(), h->work_dev(), h->cur, h->parts(), h->ctr());
     else
-        k_batch_step2d<R, DEV, false><<<h->nwork, tile2_threads<kBTX, kBTY>(), 0, s>>>(h->doms_dev(), h->work_dev(),
-                                                                                     h->cur, h->parts(), h->ctr());
+        k_batch_step2d<R, DEV, false, TL><<<h->nwork, tile2_threads<kBTX, kBTY>(), 0, s>>>(
+            h->doms_dev(), h->work_dev(), h->cur, h->parts(), h->ctr());
     return hipGetLastError();
 }
 
 hipError_t batch_enqueue_step(rtlbfs_batch_t h, bool res, hipStream_t s) {
     hipError_t e;
+    const bool tl = h->opts.method == RTLBFS_METHOD_TLBFS;
     switch (h->opts.precision) {
-        case RTLBFS_FP64_PLAIN: e = batch_launch<double, false>(h, res, s); break;
-        case RTLBFS_FP64_DEV: e = batch_launch<double, true>(h, res, s); break;
-        default: e = batch_launch<float, true>(h, res, s); break;
+        case RTLBFS_FP64_PLAIN:
+            e = tl ? batch_launch<double, false, true>(h, res, s) : batch_launch<double, false, false>(h, res, s);
+            break;
+        case RTLBFS_FP64_DEV:
+            e = tl ? batch_launch<double, true, true>(h, res, s) : batch_launch<double, true, false>(h, res, s);
+            break;
+        default:
+            e = tl ? batch_launch<float, true, true>(h, res, s) : batch_launch<float, true, false>(h, res, s);
+            break;
     }
     if (e != hipSuccess) return e;
     h->cur ^= 1;

@@ -249,6 +249,137 @@ __host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> 
     out[D + 1] = fe;
 }
 
+// TLBFS interface flux per unit area along +n (Sec. 2.2, Eqs. 29-40), same
+// arguments and frame as face_flux.  The lattice node at offset o streams
+// along e_i = -o; its equilibria (Eqs. 3-4, D2Q9 / D3Q19 weights of Eq. 6)
+// give the predicted moments of Eqs. 30-32 and the back-node parts of the
+// fluxes of Eqs. 38-40.  The face-centre parts use the equilibrium moment
+// identities (Eqs. 7-8), which hold exactly on these lattices:
+// sum e_n f* = m*_n, sum e_a e_n f* = c_s^2 rho* d_an + m*_a m*_n / rho*,
+// sum e_n g* = E* m*_n / rho*.
+// With deviation storage every sum is carried without its O(1) part: the
+// node equilibrium w rho (1 + A) enters as w phi, phi = A + r (1 + A), whose
+// plain sums differ from the full ones by the lattice constants sum w = 1,
+// sum w e = 0 and sum w e e = c_s^2 I; the energy is carried as theta with
+// rho T = T0 rho + theta and the theta flux Q - T0 P assembled from small
+// terms (A = e.u / c_s^2 + (e.u)^2 / 2c_s^4 - u^2 / 2c_s^2, B = e.u / c_s^2).
+template <typename R, int D, bool DEV>
+__host__ __device__ inline void face_flux_tlbfs(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR,
+                                       const R (&fdir)[D], const Phys<R> &ph, R (&out)[D + 2]) {
+    constexpr int NP = D + 2;
+    const R cs2 = (R)kCs2;
+    const R half = (R)0.5;
+    R base[3][NP], slope[3][D][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        base[0][p] = L.v[p] + L.g[0][p] * (dL - ph.h);
+        base[2][p] = Rt.v[p] + Rt.g[0][p] * (ph.h - dR);
+        base[1][p] = half * ((L.v[p] + L.g[0][p] * dL) + (Rt.v[p] - Rt.g[0][p] * dR));
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            slope[0][k][p] = ph.h * L.g[k][p];
+            slope[2][k][p] = ph.h * Rt.g[k][p];
+            slope[1][k][p] = half * (slope[0][k][p] + slope[2][k][p]);
+        }
+    }
+    const R w0 = D == 2 ? (R)(4.0 / 9.0) : (R)(1.0 / 3.0);
+    const R w1 = D == 2 ? (R)(1.0 / 9.0) : (R)(1.0 / 18.0);
+    const R w2 = (R)(1.0 / 36.0);
+    // sums over the nodes: density part rs (rho* or r*), momentum ms, back-node
+    // momentum flux pb (sum e_a e_n f, or its phi part), energy es (E* or
+    // theta*), back-node energy flux qb, and (deviation) sn = sum w e_n rho C
+    R rs = 0, ms[D], pb[D], es = 0, qb = 0, sn = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) ms[k] = pb[k] = (R)0;
+    R rho_c = 0, T_c = 0;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b)
+#pragma unroll
+            for (int c = -1; c <= 1; ++c) {
+                if (D == 2 && c != 0) continue;
+                if (abs(a) + abs(b) + abs(c) > 2) continue;
+                const int o[3] = {a, b, c};
+                const int nz = (a != 0) + (b != 0) + (c != 0);
+                const R w = nz == 0 ? w0 : (nz == 1 ? w1 : w2);
+                R v[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    R x = base[a + 1][p];
+#pragma unroll
+                    for (int k = 1; k < D; ++k)
+                        if (o[k] != 0) x += (R)o[k] * slope[a + 1][k][p];
+                    v[p] = x;
+                }
+                // e_i = -o in the face frame
+                R eu = 0, uu = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    if (o[k] != 0) eu += (R)(-o[k]) * v[1 + k];
+                    uu += v[1 + k] * v[1 + k];
+                }
+                const R A = (R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * uu;
+                const R B = (R)3 * eu;
+                const R rho = DEV ? (R)1 + v[0] : v[0];
+                if (nz == 0) {
+                    rho_c = rho;
+                    T_c = v[D + 1];
+                }
+                if (DEV) {
+                    const R phi = w * (A + v[0] * ((R)1 + A));
+                    const R th = rho * v[D + 1];      // theta at the node
+                    const R C = (R)1.5 * uu - (R)4.5 * eu * eu;  // B - A
+                    const R g = w * th * ((R)1 + B);
+                    rs += phi;
+                    es += g + (R)kT0 * w * rho * C;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        if (o[k] != 0) ms[k] += (R)(-o[k]) * phi;
+                    if (a != 0) {
+                        const R en = (R)(-a);
+#pragma unroll
+                        for (int k = 0; k < D; ++k)
+                            if (o[k] != 0) pb[k] += en * (R)(-o[k]) * phi;
+                        qb += en * g;
+                        sn += en * w * rho * C;
+                    }
+                } else {
+                    const R f = w * rho * ((R)1 + A);
+                    const R g = w * rho * v[D + 1] * ((R)1 + B);
+                    rs += f;
+                    es += g;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        if (o[k] != 0) ms[k] += (R)(-o[k]) * f;
+                    if (a != 0) {
+                        const R en = (R)(-a);
+#pragma unroll
+                        for (int k = 0; k < D; ++k)
+                            if (o[k] != 0) pb[k] += en * (R)(-o[k]) * f;
+                        qb += en * g;
+                    }
+                }
+            }
+    // buoyancy in the predicted momentum, at the face centre (Eq. 64)
+    const R Fb = ph.bg * rho_c * (DEV ? T_c : T_c - (R)kT0);
+    const R dt = ph.dtl;
+#pragma unroll
+    for (int k = 0; k < D; ++k) ms[k] += dt * fdir[k] * Fb;
+    const R rhos = DEV ? (R)1 + rs : rs;
+    const R inv_rhos = (R)1 / rhos;
+    const R cf = (R)1.5 - ph.tau_f, df = half - ph.tau_f;
+    const R cg = (R)1.5 - ph.tau_g, dg = half - ph.tau_g;
+    out[0] = ms[0];                                                  // Eq. 38
+#pragma unroll
+    for (int k = 0; k < D; ++k)                                      // Eq. 39
+        out[1 + k] = cf * ((k == 0 ? cs2 * rs : (R)0) + ms[k] * ms[0] * inv_rhos) - df * pb[k];
+    if (DEV)                                                         // Eq. 40, as Q - T0 P
+        out[D + 1] = cg * es * ms[0] * inv_rhos - dg * ((R)kT0 * (sn - dt * fdir[0] * Fb) + qb);
+    else
+        out[D + 1] = cg * es * ms[0] * inv_rhos - dg * qb;
+}
+
 // Wall flux per unit area along +axis for the cell P next to a no-slip wall
 // (outward normal sgn * e_axis, centre-to-wall distance d): no mass flux,
 // pressure c_s^2 r on the normal, one-sided viscous stress with

@@ -6,7 +6,8 @@
 //   2. Eq. 55 gradients (Eq. 56 face values, wall values on walls) for the
 //      tile plus a 1-cell halo;
 //   3. every face of the tile once: interior / periodic faces by the lattice
-//      predictor-corrector, wall faces by the wall closure; area-weighted
+//      predictor-corrector (RTLBFS, or TLBFS when TL), wall faces by the wall
+//      closure; area-weighted
 //      fluxes go to LDS and are shared by the two cells of the face;
 //   4. divergence, Boussinesq source, forward-Euler update (Eqs. 57-59, 64),
 //      and on residual steps the FP64 partial sums of Eq. 65.
@@ -38,7 +39,7 @@ __device__ inline int xcd_tile(int b, int nb) {
     return (b % kXcd) * (full / kXcd) + b / kXcd;
 }
 
-template <typename R, bool DEV, int TX, int TY, bool RES>
+template <typename R, bool DEV, int TX, int TY, bool RES, bool TL>
 __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, const R *__restrict__ Uin,
                                              R *__restrict__ Uout, double *__restrict__ part, uint32_t step_key) {
     constexpr int PX = TX + 4, PY = TY + 4;  // primitives with a 2-cell halo
@@ -216,7 +217,8 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                 const int na = isx ? 0 : 1, ta = isx ? 1 : 0;
                 const R fdir[2] = {(d.force_pred && d.gaxis == na) ? (R)1 : (R)0,
                                    (d.force_pred && d.gaxis == ta) ? (R)1 : (R)0};
-                face_flux<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
+                if constexpr (TL) face_flux_tlbfs<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
+                else face_flux<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
             }
             // back to global components (mass, m_x, m_y, energy)
             sf[0][tid] = G[0] * area;

@@ -1,12 +1,12 @@
 // step3d.h -- one fused RTLBFS step over a TX x TY x TZ tile of a 3D domain
 // (D3Q19 face lattice).  Same phases as the 2D tile: LDS-staged primitives
 // with a 2-cell halo, Eq. 55 gradients with a 1-cell halo, every face of the
-// tile once (lattice predictor-corrector or wall closure) into LDS, then the
-// divergence, buoyancy and forward-Euler update with optional FP64 Eq. 65
-// partial sums.  As in 2D, the faces of all three axes run one code path
-// (the face frame is chosen per lane through LDS addresses and selects, never
-// by indexing a private array at run time), and neighbour values are read
-// without branches.
+// tile once (RTLBFS or, when TL, TLBFS lattice flux, or the wall closure)
+// into LDS, then the divergence, buoyancy and forward-Euler update with
+// optional FP64 Eq. 65 partial sums.  As in 2D, the faces of all three axes
+// run one code path (the face frame is chosen per lane through LDS addresses
+// and selects, never by indexing a private array at run time), and neighbour
+// values are read without branches.
 #pragma once
 
 #include "rtlbfs_device.h"
@@ -35,22 +35,22 @@ constexpr int tile3_threads() {
     return (((TX + 1) * TY * TZ + TX * (TY + 1) * TZ + TX * TY * (TZ + 1)) + 63) / 64 * 64;
 }
 
-template <typename R, bool DEV, int TX, int TY, int TZ, bool RES>
+template <typename R, bool DEV, int TX, int TY, int TZ, bool RES, bool TL>
 __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, int k0, const R *__restrict__ Uin,
                                              R *__restrict__ Uout, double *__restrict__ part, uint32_t step_key) {
-    using TL = Tile3<TX, TY, TZ>;
+    using TT = Tile3<TX, TY, TZ>;
     constexpr int NPRIM = 5;
     constexpr int NT = tile3_threads<TX, TY, TZ>();
-    constexpr int NIT = (TL::NP + NT - 1) / NT;  // passes of the load phase
-    static_assert(TL::NG <= NT && TL::NF <= NT && TL::NC <= NT && TL::GEO <= NT,
+    constexpr int NIT = (TT::NP + NT - 1) / NT;  // passes of the load phase
+    static_assert(TT::NG <= NT && TT::NF <= NT && TT::NC <= NT && TT::GEO <= NT,
                   "gradient, face and update phases are one pass of the block");
-    __shared__ R sp[NPRIM][TL::NP];
-    __shared__ R sg[NPRIM][3][TL::NG];
-    __shared__ R sf[NPRIM][TL::NF];
-    __shared__ R sc[NPRIM][TL::NC];  // old conserved state of the tile cells
-    __shared__ R sgeo[kGeoFields][TL::GEO];
+    __shared__ R sp[NPRIM][TT::NP];
+    __shared__ R sg[NPRIM][3][TT::NG];
+    __shared__ R sf[NPRIM][TT::NF];
+    __shared__ R sc[NPRIM][TT::NC];  // old conserved state of the tile cells
+    __shared__ R sgeo[kGeoFields][TT::GEO];
     __shared__ double sred[kPartials * 16];
-    constexpr int off1 = TL::PX, off2 = TL::PX + TL::PY;  // start of the y and z halo lines in sgeo
+    constexpr int off1 = TT::PX, off2 = TT::PX + TT::PY;  // start of the y and z halo lines in sgeo
 
     const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
     const bool px = d.periodic[0], py = d.periodic[1], pz = d.periodic[2];
@@ -66,24 +66,24 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int q = tid + it * NT;
-            const int lx = q % TL::PX, ly = (q / TL::PX) % TL::PY, lz = q / (TL::PX * TL::PY);
+            const int lx = q % TT::PX, ly = (q / TT::PX) % TT::PY, lz = q / (TT::PX * TT::PY);
             int gx = i0 - 2 + lx, gy = j0 - 2 + ly, gz = k0 - 2 + lz;
             if (px) gx = wrap(gx, nx);
             if (py) gy = wrap(gy, ny);
             if (pz) gz = wrap(gz, nz);
-            ld[it] = q < TL::NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+            ld[it] = q < TT::NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
             if (ld[it]) {
                 const int64_t c = ((int64_t)gz * ny + gy) * nx + gx;
 #pragma unroll
                 for (int k = 0; k < NPRIM; ++k) st[it][k] = Uin[k * N + c];
             }
         }
-        const int ga = tid < TL::PX ? 0 : (tid < off2 ? 1 : 2);
+        const int ga = tid < TT::PX ? 0 : (tid < off2 ? 1 : 2);
         const int gl = tid - (ga == 0 ? 0 : (ga == 1 ? off1 : off2));
         const int gn = ga == 0 ? nx : (ga == 1 ? ny : nz);
         int g = (ga == 0 ? i0 : (ga == 1 ? j0 : k0)) - 2 + gl;
         if (ga == 0 ? px : (ga == 1 ? py : pz)) g = wrap(g, gn);
-        const bool lg = tid < TL::GEO && g >= 0 && g < gn;
+        const bool lg = tid < TT::GEO && g >= 0 && g < gn;
         R gv[kGeoFields];
         if (lg) {
             const R *src = (const R *)(ga == 0 ? d.geo[0] : (ga == 1 ? d.geo[1] : d.geo[2]));
@@ -94,7 +94,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         for (int it = 0; it < NIT; ++it) {
             if (!ld[it]) continue;
             const int q = tid + it * NT;
-            const int lx = q % TL::PX, ly = (q / TL::PX) % TL::PY, lz = q / (TL::PX * TL::PY);
+            const int lx = q % TT::PX, ly = (q / TT::PX) % TT::PY, lz = q / (TT::PX * TT::PY);
             const R r = st[it][0];
             const R inv_rho = (R)1 / (DEV ? (R)1 + r : r);
             sp[0][q] = r;
@@ -118,19 +118,19 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     // values (wall faces: r_S = r_P, u_S = 0, T_S = T_w if isothermal else
     // T_P).  Halo entries beyond a wall hold no data; they are read but never
     // used.
-    if (tid < TL::NG) {
-        const int lx = tid % TL::GX, ly = (tid / TL::GX) % TL::GY, lz = tid / (TL::GX * TL::GY);
+    if (tid < TT::NG) {
+        const int lx = tid % TT::GX, ly = (tid / TT::GX) % TT::GY, lz = tid / (TT::GX * TT::GY);
         int gx = i0 - 1 + lx, gy = j0 - 1 + ly, gz = k0 - 1 + lz;
         if (px) gx = wrap(gx, nx);
         if (py) gy = wrap(gy, ny);
         if (pz) gz = wrap(gz, nz);
         if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
-            const int pc = TL::pidx(lx + 1, ly + 1, lz + 1);
+            const int pc = TT::pidx(lx + 1, ly + 1, lz + 1);
             const int gq[3] = {gx, gy, gz};
             const int nq[3] = {nx, ny, nz};
             const bool pq[3] = {px, py, pz};
             const int lpos[3] = {lx + 1, ly + 1 + off1, lz + 1 + off2};  // positions in sgeo
-            constexpr int step[3] = {1, TL::PX, TL::PX * TL::PY};
+            constexpr int step[3] = {1, TT::PX, TT::PX * TT::PY};
             R vP[NPRIM];
 #pragma unroll
             for (int p = 0; p < NPRIM; ++p) vP[p] = sp[p][pc];
@@ -164,9 +164,9 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     // Phase 3: every face once.  Per lane: normal axis ax with tangents
     // (t1, t2) in increasing order, face coordinates f (the high cell's tile
     // coordinates), and the LDS strides of one step along ax.
-    if (tid < TL::NF) {
-        const int ax = tid < TL::NF0 ? 0 : (tid < TL::NF0 + TL::NF1 ? 1 : 2);
-        const int qq = tid - (ax == 0 ? 0 : (ax == 1 ? TL::NF0 : TL::NF0 + TL::NF1));
+    if (tid < TT::NF) {
+        const int ax = tid < TT::NF0 ? 0 : (tid < TT::NF0 + TT::NF1 ? 1 : 2);
+        const int qq = tid - (ax == 0 ? 0 : (ax == 1 ? TT::NF0 : TT::NF0 + TT::NF1));
         // decompositions with compile-time divisors, then a select
         const int fx = ax == 0 ? qq % (TX + 1) : qq % TX;
         const int fy = ax == 0 ? (qq / (TX + 1)) % TY : (ax == 1 ? (qq / TX) % (TY + 1) : (qq / TX) % TY);
@@ -179,15 +179,15 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
             const int fa = ax == 0 ? fx : (ax == 1 ? fy : fz);          // face coordinate along ax
             const int na = ax == 0 ? nx : (ax == 1 ? ny : nz);
             const bool pa = ax == 0 ? px : (ax == 1 ? py : pz);
-            const int sP = ax == 0 ? 1 : (ax == 1 ? TL::PX : TL::PX * TL::PY);
-            const int sG = ax == 0 ? 1 : (ax == 1 ? TL::GX : TL::GX * TL::GY);
+            const int sP = ax == 0 ? 1 : (ax == 1 ? TT::PX : TT::PX * TT::PY);
+            const int sG = ax == 0 ? 1 : (ax == 1 ? TT::GX : TT::GX * TT::GY);
             const int oa = ax == 0 ? 0 : (ax == 1 ? off1 : off2);        // sgeo line of ax
             // tangents: ax 0 -> (y, z), 1 -> (x, z), 2 -> (x, y)
             const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
             const int lt1 = ax == 0 ? fy + 2 + off1 : fx + 2;              // sgeo positions of the tangents
             const int lt2 = ax == 2 ? fy + 2 + off1 : fz + 2 + off2;
             const R area = sgeo[kGeoW][lt1] * sgeo[kGeoW][lt2];
-            const int pR = TL::pidx(fx + 2, fy + 2, fz + 2), pL = pR - sP;
+            const int pR = TT::pidx(fx + 2, fy + 2, fz + 2), pL = pR - sP;
             // local primitive order: r, u_n, u_t1, u_t2, T
             const int pm[5] = {0, 1 + ax, 1 + t1, 1 + t2, 4};
             R G[5];
@@ -210,7 +210,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, kind == kIsothermal, (R)twd, ph, G);
             } else {
                 Side<R, 3> A, B;
-                const int gR = TL::gidx(fx + 1, fy + 1, fz + 1), gL = gR - sG;
+                const int gR = TT::gidx(fx + 1, fy + 1, fz + 1), gL = gR - sG;
                 const int am[3] = {ax, t1, t2};
 #pragma unroll
                 for (int p = 0; p < 5; ++p) {
@@ -227,7 +227,8 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 R fdir[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) fdir[k] = (d.force_pred && d.gaxis == am[k]) ? (R)1 : (R)0;
-                face_flux<R, 3, DEV>(A, B, dL, dR, fdir, ph, G);
+                if constexpr (TL) face_flux_tlbfs<R, 3, DEV>(A, B, dL, dR, fdir, ph, G);
+                else face_flux<R, 3, DEV>(A, B, dL, dR, fdir, ph, G);
             }
             // back to global components (mass, m_x, m_y, m_z, energy)
             sf[0][tid] = G[0] * area;
@@ -242,16 +243,16 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     // Phase 4: divergence, Boussinesq source and update.
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const R dtR = (R)d.dt;
-    if (tid < TL::NC) {
+    if (tid < TT::NC) {
         const int x = tid % TX, y = (tid / TX) % TY, z = tid / (TX * TY);
         const int gx = i0 + x, gy = j0 + y, gz = k0 + z;
         if (gx < nx && gy < ny && gz < nz) {
             const int64_t c = ((int64_t)gz * ny + gy) * nx + gx;
             const R dt_dV = dtR * sgeo[kGeoInvW][x + 2] * sgeo[kGeoInvW][off1 + y + 2] * sgeo[kGeoInvW][off2 + z + 2];
             const int o0 = (z * TY + y) * (TX + 1) + x;                  // west face
-            const int o1 = TL::NF0 + (z * (TY + 1) + y) * TX + x;        // south face
-            const int o2 = TL::NF0 + TL::NF1 + (z * TY + y) * TX + x;    // bottom face
-            const int pc = TL::pidx(x + 2, y + 2, z + 2);
+            const int o1 = TT::NF0 + (z * (TY + 1) + y) * TX + x;        // south face
+            const int o2 = TT::NF0 + TT::NF1 + (z * TY + y) * TX + x;    // bottom face
+            const int pc = TT::pidx(x + 2, y + 2, z + 2);
             const R rP = sp[0][pc];
             const R rhoP = DEV ? (R)1 + rP : rP;
             const R TP = sp[4][pc];

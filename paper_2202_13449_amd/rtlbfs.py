@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4
 PERIODIC, WALL_ISOTHERMAL, WALL_ADIABATIC = 0, 1, 2
 FP64_PLAIN, FP32_DEV, FP64_DEV = 0, 1, 2
 INIT_REST, INIT_CONDUCTION = 0, 1
+METHOD_RTLBFS, METHOD_TLBFS = 0, 1
 
 
 class Mesh(C.Structure):
@@ -47,6 +48,7 @@ class Opts(C.Structure):
         ("beta_g", C.c_double),
         ("tile", C.c_int),
         ("round_nearest", C.c_int),
+        ("method", C.c_int),
     ]
 
 

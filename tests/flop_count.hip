@@ -1,4 +1,5 @@
-// Host-side operation count of the interior-face flux of the GPU library:
+// Host-side operation count of the interior-face fluxes (RTLBFS and TLBFS) of
+// the GPU library:
 // the face function is instantiated with a number type that counts every
 // addition, subtraction, multiplication and division.  Test infrastructure.
 #include <cstdio>
@@ -20,7 +21,7 @@ struct CountedReal {
 };
 long CountedReal::adds = 0, CountedReal::muls = 0, CountedReal::divs = 0;
 
-template <int D, bool DEV>
+template <int D, bool DEV, bool TL>
 void count(const char *name) {
     using R = CountedReal;
     rtlbfs::Side<R, D> L, Rt;
@@ -39,14 +40,19 @@ void count(const char *name) {
     for (int k = 0; k < D; ++k) fdir[k] = k == 1 ? 1.0 : 0.0;
     R out[D + 2];
     R::adds = R::muls = R::divs = 0;
-    rtlbfs::face_flux<R, D, DEV>(L, Rt, R(0.5), R(0.5), fdir, ph, out);
+    if (TL) rtlbfs::face_flux_tlbfs<R, D, DEV>(L, Rt, R(0.5), R(0.5), fdir, ph, out);
+    else rtlbfs::face_flux<R, D, DEV>(L, Rt, R(0.5), R(0.5), fdir, ph, out);
     std::printf("%s %ld %ld %ld\n", name, R::adds, R::muls, R::divs);
 }
 
 int main() {
-    count<2, false>("2d_plain");
-    count<2, true>("2d_dev");
-    count<3, false>("3d_plain");
-    count<3, true>("3d_dev");
+    count<2, false, false>("2d_plain");
+    count<2, true, false>("2d_dev");
+    count<3, false, false>("3d_plain");
+    count<3, true, false>("3d_dev");
+    count<2, false, true>("tlbfs_2d_plain");
+    count<2, true, true>("tlbfs_2d_dev");
+    count<3, false, true>("tlbfs_3d_plain");
+    count<3, true, true>("tlbfs_3d_dev");
     return 0;
 }

@@ -25,12 +25,13 @@ FP64_TOL = 1e-12
 
 
 def make_pair(dim, n, stretch, kind, Tdev, gaxis, Ra=1e4, Pr=0.71, Ma=0.1, precision=rt.FP64_PLAIN, seed=1,
-              noise=1e-3, init=INIT_REST, dtl=1.0, dt=0.0, residual_every=100, graph_steps=0, L_axis=None):
+              noise=1e-3, init=INIT_REST, dtl=1.0, dt=0.0, residual_every=100, graph_steps=0, L_axis=None,
+              method=rt.METHOD_RTLBFS):
     """A GPU solver and an oracle run of the same problem (the oracle is given
     the parameters the library derived, read back through rtlbfs_get_info)."""
     s = rt.Solver(dim, n, stretch, kind, Tdev, gaxis, Ra=Ra, Pr=Pr, Ma=Ma, precision=precision, seed=seed,
                   noise_amp=noise, init=init, dtl=dtl, dt=dt, residual_every=residual_every,
-                  graph_steps=graph_steps)
+                  graph_steps=graph_steps, method=method)
     info = s.info
     # independent derivation of Eq. 63 on the oracle side
     La = info.L
@@ -40,7 +41,8 @@ def make_pair(dim, n, stretch, kind, Tdev, gaxis, Ra=1e4, Pr=0.71, Ma=0.1, preci
     cfg = OracleConfig(dim=dim, n=tuple(n) + (1,) * (3 - len(n)), stretch=tuple(stretch) + (0.0,) * (3 - len(stretch)),
                        bc=tuple(kind) + (0,) * (6 - len(kind)), Tw=tuple(Tdev) + (0.0,) * (6 - len(Tdev)),
                        gravity_axis=gaxis, nu=nu, chi=chi, beta_g=bg, dtl=info.dtl, dt=info.dt,
-                       deviation=0 if precision == rt.FP64_PLAIN else 1, init=init, seed=seed, noise_amp=noise)
+                       deviation=0 if precision == rt.FP64_PLAIN else 1, init=init, seed=seed, noise_amp=noise,
+                       method=method)
     return s, Oracle(cfg)
 
 
@@ -290,3 +292,63 @@ def test_fp32_stochastic_rounding_removes_the_steady_state_bias():
         e_rn = abs(c[k] - a[k]) / abs(a[k])
         assert e_sr <= 1e-4, (k, e_sr)
         assert e_sr < e_rn, (k, e_sr, e_rn)
+
+
+# ------------------------------------------------------------------ TLBFS --
+
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP64_DEV])
+@pytest.mark.parametrize("shape,stretch", [((64, 64), (0.0, 0.0)), ((70, 45), (1.5, 1.5))])
+def test_tlbfs_fp64_cavity_parity(prec, shape, stretch):
+    """The TLBFS interface flux (Sec. 2.2) on the GPU against the oracle's,
+    same cavity set-up as the RTLBFS parity runs."""
+    s, o = make_pair(2, shape, stretch, Ra=1e5, precision=prec, method=rt.METHOD_TLBFS, **DHC2)
+    s.step(300)
+    o.step(300)
+    assert max(field_rel(s, o, 2)) <= 1e-11
+
+
+def test_tlbfs_fp64_periodic_rayleigh_benard_and_random_state():
+    bc = (0, 0, 1, 1)
+    s, o = make_pair(2, (48, 24), (0.0, 0.0), bc, (0.0, 0.0, 0.5, -0.5), 1, Ra=5e4, init=INIT_CONDUCTION,
+                     method=rt.METHOD_TLBFS)
+    s.step(400)
+    o.step(400)
+    assert max(field_rel(s, o, 2)) <= 1e-11
+    N = 33 * 21
+    kind = (1, 2, 2, 1)
+    s, o = make_pair(2, (33, 21), (1.5, 0.0), kind, (0.3, 0.0, 0.0, -0.2), 0, Ra=1e4, method=rt.METHOD_TLBFS,
+                     precision=rt.FP64_DEV)
+    rho, u, T = inputs.random_state(N, 2, seed=11)
+    s.set_state(rho, u, T)
+    o.set_prim(rho, u, T)
+    s.step(50)
+    o.step(50)
+    assert max(field_rel(s, o, 2)) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP64_DEV])
+def test_tlbfs_fp64_3d_cavity_parity(prec):
+    s, o = make_pair(3, (20, 14, 12), (1.5, 1.5, 1.5), (1, 1, 2, 2, 2, 2), (0.5, -0.5, 0, 0, 0, 0), 2, Ra=1e5,
+                     precision=prec, method=rt.METHOD_TLBFS)
+    s.step(150)
+    o.step(150)
+    assert max(field_rel(s, o, 3)) <= 1e-11
+
+
+def test_tlbfs_fp32_short_horizon_and_tiles():
+    """FP32 deviation TLBFS against the FP64 oracle over a short horizon, and
+    every tile shape gives the same state."""
+    s, o = make_pair(2, (70, 45), (1.5, 1.5), Ra=1e5, precision=rt.FP32_DEV, method=rt.METHOD_TLBFS, **DHC2)
+    s.step(500)
+    o.step(500)
+    assert max(field_rel(s, o, 2)) <= 1e-4
+    ref = None
+    for tile in range(1, 6):
+        t = rt.Solver(2, (70, 45), (1.5, 1.5), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"], Ra=1e5,
+                      precision=rt.FP32_DEV, seed=1, noise_amp=1e-3, tile=tile, method=rt.METHOD_TLBFS)
+        t.step(200)
+        st = [t.stored(f) for f in range(4)]
+        if ref is None:
+            ref = st
+        for a, b in zip(st, ref):
+            assert np.array_equal(a, b)
