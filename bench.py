@@ -385,6 +385,70 @@ def methods_bench(rt, torch, steps, warmup):
     return out
 
 
+STAB_RA = (1e3, 1e4, 1e5, 1e6, 1e7, 1e8)
+STAB_DTL = (0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
+STAB_N = (10, 20, 30, 40, 60, 80, 100)
+
+
+def stability_sweep(rt, members, dtl, method, max_steps, check_every=5000, tol=1e-9):
+    """Run the cavities `members` [(N, Ra)] as one FP64 batch (uniform mesh,
+    Pr = 0.71, V_c = 0.1, Delta t = 0.5, lattice step dtl) until each has
+    converged (both Eq. 65 ratios below tol) or diverged (NaN/Inf or Mach >
+    0.5), or max_steps passed: 'C', 'D' or 'U' per member."""
+    from paper_2202_13449_amd.workloads import CAVITY_GRAVITY, CAVITY_KIND, CAVITY_TDEV
+
+    meshes = [rt.make_mesh(2, (n, n), (0.0, 0.0)) for n, _ in members]
+    bcs = [rt.make_bc(CAVITY_KIND, CAVITY_TDEV, CAVITY_GRAVITY) for _ in members]
+    b = rt.Batch(meshes, [ra for _, ra in members], [0.71] * len(members), bcs, Ma=MA, precision=rt.FP64_PLAIN,
+                 seed=1, noise_amp=1e-6, dtl=dtl, dt=0.5, method=method, residual_every=100)
+    state = ["U"] * len(members)
+    done = 0
+    while done < max_steps and "U" in state:
+        b.step(check_every)
+        done += check_every
+        div = b.diverged()
+        res = b.residuals()
+        for k in range(len(members)):
+            if state[k] != "U":
+                continue
+            if div[k] or not np.all(np.isfinite(res[k])):
+                state[k] = "D"
+            elif res[k].max() < tol:
+                state[k] = "C"
+    del b
+    return state, done
+
+
+def stability_bench(rt, torch, steps, warmup, max_steps=600_000):
+    """The stability maps of Sec. 3.3 as batched launches, FP64, for RTLBFS
+    and TLBFS: Fig. 4 (50^2, Delta t = 0.5, lattice step dtl x Ra) and Fig. 5
+    (dtl = 1, mesh N x Ra).  Rows are printed as strings of C (converged to
+    1e-9), D (diverged), U (neither within the step budget)."""
+    out = {"workload": "stability maps, Sec. 3.3", "Ra": list(STAB_RA), "max_steps": max_steps}
+    t0 = time.perf_counter()
+    for mname, method in (("rtlbfs", rt.METHOD_RTLBFS), ("tlbfs", rt.METHOD_TLBFS)):
+        fig4 = {}
+        for dtl in STAB_DTL:
+            st, n = stability_sweep(rt, [(50, ra) for ra in STAB_RA], dtl, method, max_steps)
+            fig4[f"{dtl:.1f}"] = "".join(st)
+            print(json.dumps({"fig4": mname, "dtl": dtl, "row": "".join(st), "steps": n,
+                              "s": round(time.perf_counter() - t0, 1)}), flush=True)
+        members = [(n, ra) for n in STAB_N for ra in STAB_RA]
+        st, n = stability_sweep(rt, members, 1.0, method, max_steps)
+        fig5 = {str(N): "".join(st[i * len(STAB_RA):(i + 1) * len(STAB_RA)]) for i, N in enumerate(STAB_N)}
+        print(json.dumps({"fig5": mname, "rows": fig5, "steps": n, "s": round(time.perf_counter() - t0, 1)}),
+              flush=True)
+        out[mname] = {"fig4_dtl_by_Ra": fig4, "fig5_N_by_Ra": fig5}
+    a4 = "".join(out["rtlbfs"]["fig4_dtl_by_Ra"].values())
+    b4 = "".join(out["tlbfs"]["fig4_dtl_by_Ra"].values())
+    a5 = "".join(out["rtlbfs"]["fig5_N_by_Ra"].values())
+    b5 = "".join(out["tlbfs"]["fig5_N_by_Ra"].values())
+    out["agreement_fig4"] = sum(x == y for x, y in zip(a4, b4)) / len(a4)
+    out["agreement_fig5"] = sum(x == y for x, y in zip(a5, b5)) / len(a5)
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
 def steady_bench(rt, torch, steps, warmup, tol=1e-8, max_steps=4_000_000, chunk=20000):
     """The 256^2 cavity run to steady state: FP64 plain until both Eq. 65
     ratios are below tol, then FP32 deviation for the same number of steps;
@@ -449,11 +513,13 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
-    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods"],
+    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods",
+                                                           "stability"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
                          "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
                          "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5; "
-                         "hill: the Gaussian-hill convergence study of Sec. 4.1; methods: RTLBFS vs TLBFS step cost")
+                         "hill: the Gaussian-hill convergence study of Sec. 4.1; methods: RTLBFS vs TLBFS step cost; "
+                         "stability: the stability maps of Figs. 4-5 as batched runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -481,7 +547,8 @@ def main():
         return
     if args.workload != "cavity256":
         fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,
-              "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench}[args.workload]
+              "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench,
+              "stability": stability_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE

@@ -235,6 +235,14 @@ int rtlbfs_batch_residual(rtlbfs_batch_t h, int member, double *res_u, double *r
 int rtlbfs_batch_get_field(rtlbfs_batch_t h, int member, int field, double *host_out, size_t count);
 int rtlbfs_batch_get_info(rtlbfs_batch_t h, int member, rtlbfs_info *out);
 int rtlbfs_batch_sync(rtlbfs_batch_t h);
+/* Per-member divergence flags of the last residual step (synchronising):
+ * host_flags[m] = 1 when member m held a NaN/Inf or a local Mach number above
+ * 0.5 (the guard evaluated with Eq. 65), else 0.  host_flags holds `count`
+ * ints owned by the caller.  A diverged member does not disturb the others,
+ * so a parameter sweep keeps stepping the batch and reads the flags (the
+ * stability maps of Sec. 3.3, Figs. 4-5).  Returns RTLBFS_ESTATE before the
+ * first residual step, RTLBFS_OK otherwise (also when members diverged). */
+int rtlbfs_batch_diverged(rtlbfs_batch_t h, int *host_flags);
 int rtlbfs_batch_destroy(rtlbfs_batch_t h);
 
 #ifdef __cplusplus

@@ -430,6 +430,16 @@ int rtlbfs_batch_sync(rtlbfs_batch_t h) {
     return RTLBFS_OK;
 }
 
+int rtlbfs_batch_diverged(rtlbfs_batch_t h, int *host_flags) {
+    if (!h || !host_flags) return RTLBFS_EINVAL;
+    if (!h->res_valid) return bfail(h, RTLBFS_ESTATE, "no residual step yet");
+    BHIP_TRY(h, hipMemcpyAsync(h->host_buf, h->res_out(), sizeof(double) * kPartials * h->count,
+                               hipMemcpyDeviceToHost, h->stream));
+    BHIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int m = 0; m < h->count; ++m) host_flags[m] = h->host_buf[m * kPartials + 4] != 0.0 ? 1 : 0;
+    return RTLBFS_OK;
+}
+
 int rtlbfs_batch_residual(rtlbfs_batch_t h, int member, double *res_u, double *res_T) {
     int rc = check_member(h, member);
     if (rc != RTLBFS_OK) return rc;

@@ -130,12 +130,13 @@ def load_library() -> C.CDLL:
     lib.rtlbfs_batch_get_field.argtypes = [VP, I, I, PD, SZ]
     lib.rtlbfs_batch_get_info.argtypes = [VP, I, C.POINTER(Info)]
     lib.rtlbfs_batch_sync.argtypes = [VP]
+    lib.rtlbfs_batch_diverged.argtypes = [VP, C.POINTER(C.c_int)]
     lib.rtlbfs_batch_destroy.argtypes = [VP]
     for name in ("rtlbfs_opts_init", "rtlbfs_mesh_nodes", "rtlbfs_create", "rtlbfs_step", "rtlbfs_sync",
                  "rtlbfs_residual", "rtlbfs_nusselt", "rtlbfs_integrals", "rtlbfs_get_field", "rtlbfs_get_stored",
                  "rtlbfs_set_state", "rtlbfs_get_info", "rtlbfs_destroy", "rtlbfs_batch_create", "rtlbfs_batch_step",
                  "rtlbfs_batch_nusselt", "rtlbfs_batch_residual", "rtlbfs_batch_get_field", "rtlbfs_batch_get_info",
-                 "rtlbfs_batch_sync", "rtlbfs_batch_destroy"):
+                 "rtlbfs_batch_sync", "rtlbfs_batch_diverged", "rtlbfs_batch_destroy"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -345,6 +346,12 @@ class Batch:
     def sync(self):
         self._check(self._lib.rtlbfs_batch_sync(self._h), "rtlbfs_batch_sync")
 
+    def diverged(self) -> np.ndarray:
+        """Per-member divergence flags of the last residual step."""
+        flags = (C.c_int * self.count)()
+        self._check(self._lib.rtlbfs_batch_diverged(self._h, flags), "rtlbfs_batch_diverged")
+        return np.array(list(flags), dtype=bool)
+
     def info(self, k: int) -> Info:
         i = Info()
         self._check(self._lib.rtlbfs_batch_get_info(self._h, k, C.byref(i)), "rtlbfs_batch_get_info")
@@ -360,6 +367,18 @@ class Batch:
         a, b = C.c_double(), C.c_double()
         self._check(self._lib.rtlbfs_batch_residual(self._h, k, C.byref(a), C.byref(b)), "rtlbfs_batch_residual")
         return a.value, b.value
+
+    def residuals(self) -> np.ndarray:
+        """Eq. 65 residuals (count x 2) of every member, also when some
+        members diverged (theirs are NaN or meaningless; see diverged())."""
+        out = np.zeros((self.count, 2))
+        for k in range(self.count):
+            a, b = C.c_double(), C.c_double()
+            rc = self._lib.rtlbfs_batch_residual(self._h, k, C.byref(a), C.byref(b))
+            if rc not in (OK, EDIVERGED):
+                self._check(rc, "rtlbfs_batch_residual")
+            out[k] = a.value, b.value
+        return out
 
     def field(self, k: int, f: int) -> np.ndarray:
         cells = int(self.info(k).cells)
