@@ -246,6 +246,22 @@ inline void fill_domain(const Problem &p, int precision, int force_pred, int rou
     d.tau_g = 0.5 + p.chi / (kCs2 * p.dtl); // Eq. 10
     d.cells = p.cells;
     d.fstride = field_stride(p.cells);
+    Phys<double> ph;
+    ph.nu = d.nu;
+    ph.chi = d.chi;
+    ph.dtl = d.dtl;
+    ph.tau_f = d.tau_f;
+    ph.tau_g = d.tau_g;
+    ph.bg = d.bg;
+    ph.dt = d.dt;
+    ph.h = d.dtl;  // lattice spacing c * delta-t with c = 1
+    ph.inv2h = 1.0 / (2.0 * d.dtl);
+    ph.invh2 = 1.0 / (d.dtl * d.dtl);
+    ph.inv4h2 = 1.0 / (4.0 * d.dtl * d.dtl);
+    d.phd = ph;
+    d.phf = {(float)ph.nu, (float)ph.chi, (float)ph.dtl, (float)ph.tau_f, (float)ph.tau_g, (float)ph.bg,
+             (float)ph.dt, (float)ph.h, (float)ph.inv2h, (float)ph.invh2, (float)ph.inv4h2};
+    for (int s = 0; s < 6; ++s) d.Twf[s] = (float)d.Tw[s];
 }
 
 }  // namespace host

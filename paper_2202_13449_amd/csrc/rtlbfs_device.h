@@ -22,6 +22,15 @@ enum : int { kPeriodic = 0, kIsothermal = 1, kAdiabatic = 2 };
 // are unused.
 enum : int { kGeoW = 0, kGeoInvW, kGeoLoSelf, kGeoLoNb, kGeoHiSelf, kGeoHiNb, kGeoFields };
 
+// Physical and lattice constants of the step: viscosity, diffusivity, lattice
+// step, relaxation times (Eqs. 9-10), buoyancy beta*g, the time step Delta-t,
+// and the lattice spacing h = c dt with its finite-difference factors.
+template <typename R>
+struct Phys {
+    R nu, chi, dtl, tau_f, tau_g, bg, dt;
+    R h, inv2h, invh2, inv4h2;
+};
+
 // One structured domain as the kernels see it.  Lengths in lattice units;
 // Tw is in the storage convention (T - T0 for deviation storage, absolute T
 // for plain storage).
@@ -40,6 +49,9 @@ struct Domain {
     int64_t cells;       // number of cells
     int64_t fstride;     // elements between consecutive fields of one state copy
     void *U[2];          // the two state copies (used by the batched kernels)
+    Phys<float> phf;     // the constants above, in FP32 and in FP64
+    Phys<double> phd;
+    float Twf[6];        // Tw in FP32
 };
 
 // ------------------------------------------------------------ reductions --
@@ -76,28 +88,35 @@ __device__ inline void block_sums(double (&v)[K], double *scratch) {
     __syncthreads();
 }
 
+// 1/x in the kernel precision.  FP32 kernels use the hardware reciprocal
+// (v_rcp_f32, 1 ulp), which is well inside the FP32 path's own rounding
+// budget and saves the correctly rounded division sequence; FP64 (and the
+// host, where the face functions are also instantiated for operation
+// counting) divide.
+template <typename R>
+__host__ __device__ inline R recip(R x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(x);
+#endif
+    return (R)1 / x;
+}
+
 // ------------------------------------------------------------ face flux --
 
+// The physical and lattice constants of a step in the kernel precision; the
+// host fills both precisions into the Domain once, so no kernel converts or
+// divides them at run time.
 template <typename R>
-struct Phys {
-    R nu, chi, dtl, tau_f, tau_g, bg;
-    R h, inv2h, invh2, inv4h2;
-};
+__device__ inline const Phys<R> &make_phys(const Domain &d) {
+    if constexpr (sizeof(R) == 4) return d.phf;
+    else return d.phd;
+}
 
+// Wall temperature of side s (storage convention) in the kernel precision.
 template <typename R>
-__device__ inline Phys<R> make_phys(const Domain &d) {
-    Phys<R> p;
-    p.nu = (R)d.nu;
-    p.chi = (R)d.chi;
-    p.dtl = (R)d.dtl;
-    p.tau_f = (R)d.tau_f;
-    p.tau_g = (R)d.tau_g;
-    p.bg = (R)d.bg;
-    p.h = (R)d.dtl;  // lattice spacing c * delta-t with c = 1
-    p.inv2h = (R)(1.0 / (2.0 * d.dtl));
-    p.invh2 = (R)(1.0 / (d.dtl * d.dtl));
-    p.inv4h2 = (R)(1.0 / (4.0 * d.dtl * d.dtl));
-    return p;
+__device__ inline R wall_T(const Domain &d, int s) {
+    if constexpr (sizeof(R) == 4) return d.Twf[s];
+    else return d.Tw[s];
 }
 
 // One side of a face: cell-centre primitives (r, u_0..u_{D-1}, T) in the
@@ -231,7 +250,7 @@ __host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> 
     }
     const R de = -dt * divq + cs2 * dt2h * lape;
     const R rhos = rho0 + dr, es = e0 + de;
-    const R inv_rhos = (R)1 / rhos;
+    const R inv_rhos = recip(rhos);
     // Eqs. 57-59.
     out[0] = ms[0];
 #pragma unroll
@@ -367,7 +386,7 @@ __host__ __device__ inline void face_flux_tlbfs(const Side<R, D> &L, const Side<
 #pragma unroll
     for (int k = 0; k < D; ++k) ms[k] += dt * fdir[k] * Fb;
     const R rhos = DEV ? (R)1 + rs : rs;
-    const R inv_rhos = (R)1 / rhos;
+    const R inv_rhos = recip(rhos);
     const R cf = (R)1.5 - ph.tau_f, df = half - ph.tau_f;
     const R cg = (R)1.5 - ph.tau_g, dg = half - ph.tau_g;
     out[0] = ms[0];                                                  // Eq. 38
@@ -390,7 +409,7 @@ template <typename R, int D, bool DEV>
 __host__ __device__ inline void wall_flux(R rP, const R (&m)[D], R eP, R sgn, R d, bool iso, R Tw, const Phys<R> &ph,
                                  R (&out)[D + 2]) {
     const R rho = DEV ? (R)1 + rP : rP;
-    const R inv_d = (R)1 / d;
+    const R inv_d = recip(d);
     out[0] = (R)0;
     out[1] = (R)kCs2 * rP + sgn * (R)3 * ph.nu * m[0] * inv_d;
 #pragma unroll

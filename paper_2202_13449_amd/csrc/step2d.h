@@ -62,7 +62,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     const bool px = d.periodic[0], py = d.periodic[1];
     const R *__restrict__ geox = (const R *)d.geo[0];
     const R *__restrict__ geoy = (const R *)d.geo[1];
-    const Phys<R> ph = make_phys<R>(d);
+    const Phys<R> &ph = make_phys<R>(d);
     const int tid = threadIdx.x;
 
     // Phase 1: state of the tile and halo, then the geometry of the halo
@@ -94,7 +94,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
             for (int k = 0; k < kGeoFields; ++k) gv[k] = src[k * gn + g];
         }
         if (ld) {
-            const R inv_rho = (R)1 / (DEV ? (R)1 + r : r);
+            const R inv_rho = recip<R>(DEV ? (R)1 + r : r);
             const int ti = li - 2, tj = lj - 2;
             if (ti >= 0 && ti < TX && tj >= 0 && tj < TY) {
                 sc[0][tj][ti] = r;
@@ -143,10 +143,10 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                 vS[p] = sp[p][cj - 1][ci];
                 vN[p] = sp[p][cj + 1][ci];
             }
-            const R TwW = d.kind[0] == kIsothermal ? (R)d.Tw[0] : vP[3];
-            const R TwE = d.kind[1] == kIsothermal ? (R)d.Tw[1] : vP[3];
-            const R TwS = d.kind[2] == kIsothermal ? (R)d.Tw[2] : vP[3];
-            const R TwN = d.kind[3] == kIsothermal ? (R)d.Tw[3] : vP[3];
+            const R TwW = d.kind[0] == kIsothermal ? wall_T<R>(d, 0) : vP[3];
+            const R TwE = d.kind[1] == kIsothermal ? wall_T<R>(d, 1) : vP[3];
+            const R TwS = d.kind[2] == kIsothermal ? wall_T<R>(d, 2) : vP[3];
+            const R TwN = d.kind[3] == kIsothermal ? wall_T<R>(d, 3) : vP[3];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const R fw0 = vP[p] * xls + vW[p] * xln, fe0 = vP[p] * xhs + vE[p] * xhn;
@@ -197,8 +197,9 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                 const R d_w = (R)0.5 * wcell;
                 const R mloc[2] = {rho * sp[pn][wy][wx], rho * sp[pt][wy][wx]};
                 const int kind = side == 0 ? d.kind[0] : side == 1 ? d.kind[1] : side == 2 ? d.kind[2] : d.kind[3];
-                const double twd = side == 0 ? d.Tw[0] : side == 1 ? d.Tw[1] : side == 2 ? d.Tw[2] : d.Tw[3];
-                wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][wy][wx], sgn, d_w, kind == kIsothermal, (R)twd, ph, G);
+                const R twd = side == 0 ? wall_T<R>(d, 0) : side == 1 ? wall_T<R>(d, 1)
+                                        : side == 2 ? wall_T<R>(d, 2) : wall_T<R>(d, 3);
+                wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][wy][wx], sgn, d_w, kind == kIsothermal, twd, ph, G);
             } else {
                 Side<R, 2> A, B;
                 const int gn = isx ? 0 : 1, gt = isx ? 1 : 0;  // gradient components along n and t
@@ -231,7 +232,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
 
     // Phase 4: divergence, Boussinesq source and update.
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const R dtR = (R)d.dt;
+    const R dtR = ph.dt;
     if (tid < TX * TY) {
         const int lc = tid % TX, lr = tid / TX;
         const int gi = i0 + lc, gj = j0 + lr;
@@ -249,7 +250,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
 #pragma unroll
                 for (int f = 0; f < 4; ++f)
                     inc[f] = dt_dV * ((sf[f][fw] - sf[f][fw + 1]) + (sf[f][fs] - sf[f][fs + TX]));
-                if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+                if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
 #pragma unroll
                 for (int f = 0; f < 4; ++f)
                     Un[f] = sr_add(sc[f][lr][lc], inc[f], sr_hash((uint32_t)c, step_key * 4u + f));
@@ -259,7 +260,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                     const R div = (sf[f][fw] - sf[f][fw + 1]) + (sf[f][fs] - sf[f][fs + TX]);
                     Un[f] = sc[f][lr][lc] + dt_dV * div;
                 }
-                if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+                if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
             }
 #pragma unroll
             for (int f = 0; f < 4; ++f) Uout[f * N + c] = Un[f];

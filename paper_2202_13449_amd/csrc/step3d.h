@@ -55,7 +55,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
     const bool px = d.periodic[0], py = d.periodic[1], pz = d.periodic[2];
     const int64_t N = d.fstride;
-    const Phys<R> ph = make_phys<R>(d);
+    const Phys<R> &ph = make_phys<R>(d);
     const int tid = threadIdx.x;
 
     // Phase 1: state of the tile and halo (NIT passes, all loads issued
@@ -96,7 +96,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
             const int q = tid + it * NT;
             const int lx = q % TT::PX, ly = (q / TT::PX) % TT::PY, lz = q / (TT::PX * TT::PY);
             const R r = st[it][0];
-            const R inv_rho = (R)1 / (DEV ? (R)1 + r : r);
+            const R inv_rho = recip<R>(DEV ? (R)1 + r : r);
             sp[0][q] = r;
 #pragma unroll
             for (int k = 1; k < NPRIM; ++k) sp[k][q] = st[it][k] * inv_rho;
@@ -140,8 +140,8 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 const R ls = sgeo[kGeoLoSelf][lpos[a]], ln = sgeo[kGeoLoNb][lpos[a]];
                 const R hs = sgeo[kGeoHiSelf][lpos[a]], hn = sgeo[kGeoHiNb][lpos[a]];
                 const bool wlo = !pq[a] && gq[a] == 0, whi = !pq[a] && gq[a] == nq[a] - 1;
-                const R Tlo = d.kind[2 * a] == kIsothermal ? (R)d.Tw[2 * a] : vP[4];
-                const R Thi = d.kind[2 * a + 1] == kIsothermal ? (R)d.Tw[2 * a + 1] : vP[4];
+                const R Tlo = d.kind[2 * a] == kIsothermal ? wall_T<R>(d, 2 * a) : vP[4];
+                const R Thi = d.kind[2 * a + 1] == kIsothermal ? wall_T<R>(d, 2 * a + 1) : vP[4];
                 R vlo[NPRIM], vhi[NPRIM];
 #pragma unroll
                 for (int p = 0; p < NPRIM; ++p) {
@@ -201,13 +201,13 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 const R d_w = (R)0.5 * sgeo[kGeoW][oa + (low ? fa + 2 : fa + 1)];
                 const R mloc[3] = {rho * sp[pm[1]][pc], rho * sp[pm[2]][pc], rho * sp[pm[3]][pc]};
                 int kind = d.kind[0];
-                double twd = d.Tw[0];
+                R twd = wall_T<R>(d, 0);
 #pragma unroll
                 for (int s = 1; s < 6; ++s) {
                     kind = side == s ? d.kind[s] : kind;
-                    twd = side == s ? d.Tw[s] : twd;
+                    twd = side == s ? wall_T<R>(d, s) : twd;
                 }
-                wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, kind == kIsothermal, (R)twd, ph, G);
+                wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, kind == kIsothermal, twd, ph, G);
             } else {
                 Side<R, 3> A, B;
                 const int gR = TT::gidx(fx + 1, fy + 1, fz + 1), gL = gR - sG;
@@ -242,7 +242,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
 
     // Phase 4: divergence, Boussinesq source and update.
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const R dtR = (R)d.dt;
+    const R dtR = ph.dt;
     if (tid < TT::NC) {
         const int x = tid % TX, y = (tid / TX) % TY, z = tid / (TX * TY);
         const int gx = i0 + x, gy = j0 + y, gz = k0 + z;
@@ -263,7 +263,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 for (int k = 0; k < 5; ++k)
                     inc[k] = dt_dV * ((sf[k][o0] - sf[k][o0 + 1]) + (sf[k][o1] - sf[k][o1 + TX]) +
                                       (sf[k][o2] - sf[k][o2 + TX * TY]));
-                if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+                if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
 #pragma unroll
                 for (int k = 0; k < 5; ++k)
                     Un[k] = sr_add(sc[k][tid], inc[k], sr_hash((uint32_t)c, step_key * 5u + k));
@@ -274,7 +274,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                                   (sf[k][o2] - sf[k][o2 + TX * TY]);
                     Un[k] = sc[k][tid] + dt_dV * div;
                 }
-                if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * (R)d.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+                if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
             }
 #pragma unroll
             for (int k = 0; k < 5; ++k) Uout[k * N + c] = Un[k];
