@@ -56,6 +56,8 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     __shared__ R sgx[kGeoFields][PX];  // geometry of the tile columns (with halo)
     __shared__ R sgy[kGeoFields][PY];  // geometry of the tile rows (with halo)
     __shared__ double sred[kPartials * 16];
+    __shared__ R swT[4];     // wall value of T per side (T_w if isothermal, else unused)
+    __shared__ int swIso[4]; // side is an isothermal wall
 
     const int nx = d.n[0], ny = d.n[1];
     const int64_t N = d.fstride;
@@ -112,6 +114,15 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
             for (int k = 0; k < kGeoFields; ++k) {
                 if (isx) sgx[k][gl] = gv[k];
                 else sgy[k][gl] = gv[k];
+            }
+        }
+        // per-side wall data through LDS, so a lane can pick its side by
+        // index without a per-lane load from the kernel arguments
+        if (tid == 0) {  // compile-time side indices: scalar loads of the arguments
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                swT[k] = wall_T<R>(d, k);
+                swIso[k] = d.kind[k] == kIsothermal;
             }
         }
     }
@@ -196,10 +207,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
                 const R wcell = isx ? sgx[kGeoW][wx] : sgy[kGeoW][wy];
                 const R d_w = (R)0.5 * wcell;
                 const R mloc[2] = {rho * sp[pn][wy][wx], rho * sp[pt][wy][wx]};
-                const int kind = side == 0 ? d.kind[0] : side == 1 ? d.kind[1] : side == 2 ? d.kind[2] : d.kind[3];
-                const R twd = side == 0 ? wall_T<R>(d, 0) : side == 1 ? wall_T<R>(d, 1)
-                                        : side == 2 ? wall_T<R>(d, 2) : wall_T<R>(d, 3);
-                wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][wy][wx], sgn, d_w, kind == kIsothermal, twd, ph, G);
+                wall_flux<R, 2, DEV>(rP, mloc, rho * sp[3][wy][wx], sgn, d_w, swIso[side] != 0, swT[side], ph, G);
             } else {
                 Side<R, 2> A, B;
                 const int gn = isx ? 0 : 1, gt = isx ? 1 : 0;  // gradient components along n and t

@@ -50,6 +50,8 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     __shared__ R sc[NPRIM][TT::NC];  // old conserved state of the tile cells
     __shared__ R sgeo[kGeoFields][TT::GEO];
     __shared__ double sred[kPartials * 16];
+    __shared__ R swT[6];     // wall value of T per side (T_w if isothermal, else unused)
+    __shared__ int swIso[6]; // side is an isothermal wall
     constexpr int off1 = TT::PX, off2 = TT::PX + TT::PY;  // start of the y and z halo lines in sgeo
 
     const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
@@ -110,6 +112,15 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         if (lg) {
 #pragma unroll
             for (int k = 0; k < kGeoFields; ++k) sgeo[k][tid] = gv[k];
+        }
+        // per-side wall data through LDS, so a lane can pick its side by
+        // index without a per-lane load from the kernel arguments
+        if (tid == 0) {  // compile-time side indices: scalar loads of the arguments
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                swT[k] = wall_T<R>(d, k);
+                swIso[k] = d.kind[k] == kIsothermal;
+            }
         }
     }
     __syncthreads();
@@ -200,14 +211,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 const R rho = DEV ? (R)1 + rP : rP;
                 const R d_w = (R)0.5 * sgeo[kGeoW][oa + (low ? fa + 2 : fa + 1)];
                 const R mloc[3] = {rho * sp[pm[1]][pc], rho * sp[pm[2]][pc], rho * sp[pm[3]][pc]};
-                int kind = d.kind[0];
-                R twd = wall_T<R>(d, 0);
-#pragma unroll
-                for (int s = 1; s < 6; ++s) {
-                    kind = side == s ? d.kind[s] : kind;
-                    twd = side == s ? wall_T<R>(d, s) : twd;
-                }
-                wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, kind == kIsothermal, twd, ph, G);
+                wall_flux<R, 3, DEV>(rP, mloc, rho * sp[4][pc], sgn, d_w, swIso[side] != 0, swT[side], ph, G);
             } else {
                 Side<R, 3> A, B;
                 const int gR = TT::gidx(fx + 1, fy + 1, fz + 1), gL = gR - sG;
