@@ -69,7 +69,8 @@ def kernel_sources_sha256() -> str:
 
 
 def measured_traffic(tile):
-    """HBM bytes per launch of the dominant kernel (tile shape `tile`) from the
+    """HBM bytes per launch of the dominant kernel (launch shape `tile` = tile
+    x, tile y, steps per launch) from the
     committed counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its
     copy-kernel calibration); None when the kernels changed since it was
     taken."""
@@ -80,10 +81,17 @@ def measured_traffic(tile):
         return None
     if t.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
-    return t.get("bytes_per_launch_by_tile", {}).get(f"{tile[0]}x{tile[1]}")
+    key = f"{tile[0]}x{tile[1]}" + ("" if tile[2] == 1 else f"/{tile[2]}")
+    return t.get("bytes_per_launch_by_tile", {}).get(key)
 
 
-TILES_2D = {(32, 8): 1, (16, 16): 2, (64, 4): 3, (16, 8): 4, (8, 8): 5}  # opts.tile of each 2D tile shape
+# opts.tile of each 2D launch shape (tile x, tile y, steps per launch)
+TILES_2D = {(32, 8, 1): 1, (16, 16, 1): 2, (64, 4, 1): 3, (16, 8, 1): 4, (8, 8, 1): 5,
+            (16, 16, 2): 6, (32, 8, 2): 7, (16, 8, 2): 8, (8, 8, 2): 9}
+
+
+def launch_shape(info):
+    return (info.tile_x, info.tile_y, info.steps_per_launch)
 
 
 def make_solver(rt, precision, residual_every=100, mass_fix_every=1000, tile=0):
@@ -110,7 +118,7 @@ def time_step_kernel(rt, torch, precision, steps, warmup, tile):
     e1.record(stream)
     torch.cuda.synchronize()
     s.sync()
-    return e0.elapsed_time(e1) / steps, [s.info.tile_x, s.info.tile_y]
+    return e0.elapsed_time(e1) / steps, list(launch_shape(s.info))
 
 
 def time_path(rt, torch, precision, steps, warmup):
@@ -225,7 +233,7 @@ def rb_bench(rt, torch, steps, warmup):
             "total_steps": done, "finite": bool(np.isfinite(umax)), "umax": umax,
             "pass": bool(np.isfinite(umax) and umax < 0.3),
             "nu_time_avg_last_50k": avg, "nu_samples": len(samples), "nu_final": s.nusselt(),
-            "tile": [s.info.tile_x, s.info.tile_y]}
+            "tile": list(launch_shape(s.info))}
 
 
 def cube_bench(rt, torch, steps, warmup):
@@ -365,10 +373,10 @@ def methods_bench(rt, torch, steps, warmup):
             s = rt.Solver(2, (N_CELLS_SIDE, N_CELLS_SIDE), (STRETCH, STRETCH), KIND, TDEV, GAXIS, Ra=RA, Pr=PR,
                           Ma=MA, precision=prec, seed=1, noise_amp=1e-6, residual_every=KERNEL_CHUNK,
                           mass_fix_every=-1, tile=tile, method=method)
-            tile = TILES_2D[(s.info.tile_x, s.info.tile_y)]
+            tile = TILES_2D[launch_shape(s.info)]
             s.step(max(warmup, KERNEL_CHUNK))
             n = max(KERNEL_CHUNK, steps - steps % KERNEL_CHUNK)
-            res[mname] = {"us_per_step": timed(torch, s, n) * 1e3, "tile": [s.info.tile_x, s.info.tile_y]}
+            res[mname] = {"us_per_step": timed(torch, s, n) * 1e3, "tile": list(launch_shape(s.info))}
             del s
         res["rtlbfs_over_tlbfs"] = res["rtlbfs"]["us_per_step"] / res["tlbfs"]["us_per_step"]
         out[name] = res
@@ -577,7 +585,7 @@ def main():
     # roofline is the FP32 vector peak; the HBM fraction is reported beside it.
     fpl = FLOPS_PER_CELL["f32"] * cells   # algorithmic flops per step-kernel launch
     bpl = BYTES_PER_CELL["f32"] * cells   # algorithmic bytes per step-kernel launch
-    tile32 = (r32["solver"].info.tile_x, r32["solver"].info.tile_y)
+    tile32 = launch_shape(r32["solver"].info)
     kms, ktile = time_step_kernel(rt, torch, rt.FP32_DEV, args.steps, args.warmup, TILES_2D[tile32])
     achieved = fpl / (kms * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -585,11 +593,12 @@ def main():
                        "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS,
                        "frac_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS,
                        "kernel": "k_step2d<float, deviation>", "kernel_us": kms * 1e3, "kernel_tile": ktile,
+                       "steps_per_launch": ktile[2], "launch_us": kms * 1e3 * ktile[2],
                        "flops_per_cell": FLOPS_PER_CELL["f32"], "bytes_per_cell": BYTES_PER_CELL["f32"],
                        "hbm_achieved_gbs": bpl / (kms * 1e-3) / 1e9,
                        "hbm_frac": bpl / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out["nu_fp32"] = r32["nu"]
-    out["tile"] = [r32["solver"].info.tile_x, r32["solver"].info.tile_y]
+    out["tile"] = list(launch_shape(r32["solver"].info))
     if not args.fp32_only:
         r64 = time_path(rt, torch, rt.FP64_PLAIN, args.steps, args.warmup)
         ms64 = r64["event_ms"] / args.steps

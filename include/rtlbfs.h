@@ -107,8 +107,11 @@ typedef struct {
     int buoyancy_update_only; /* 1: force only in the cell update (not in m*) */
     int phys_given;       /* 1: use nu, chi, beta_g below and ignore Ra, Pr, Ma */
     double nu, chi, beta_g;
-    int tile;             /* 2D kernel tile: 0 -> autotuned at create (every shape timed on the
-                             live state); 1..5 -> 32x8, 16x16, 64x4, 16x8, 8x8 cells */
+    int tile;             /* 2D launch shape: 0 -> autotuned at create (every shape timed on the
+                             live state); 1..5 -> one step per launch on 32x8, 16x16, 64x4, 16x8,
+                             8x8 cells; 6..9 -> two steps per launch on 16x16, 32x8, 16x8, 8x8
+                             (the state of the first step stays on chip; an odd last step uses
+                             the one-step shape of the same tile) */
     int round_nearest;    /* FP32_DEV only. 0 (default): the state update u + du is rounded
                              stochastically (unbiased; random bits from a hash of cell, field and a
                              device step counter, reproducible); 1: round-to-nearest, which stalls
@@ -133,7 +136,9 @@ typedef struct {
     double length[3];           /* domain length per axis */
     int precision;
     int tile_x, tile_y, tile_z; /* tile the step kernel runs with */
-    double tune_ms[8];          /* autotuner: ms per step of each 2D tile shape (0 if not timed) */
+    double tune_ms[16];         /* autotuner: ms per step of each 2D launch shape, in opts.tile order
+                                   (0 if not timed) */
+    int steps_per_launch;       /* time steps one launch of the step kernel advances (1 or 2) */
 } rtlbfs_info;
 
 typedef struct rtlbfs_handle *rtlbfs_t;

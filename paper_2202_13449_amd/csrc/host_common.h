@@ -87,7 +87,7 @@ inline int validate(const rtlbfs_mesh *m, const rtlbfs_bc *bc, const rtlbfs_opts
     }
     if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return why = "dtl and dt must be >= 0", RTLBFS_EINVAL;
     if (o.init != RTLBFS_INIT_REST && o.init != RTLBFS_INIT_CONDUCTION) return why = "unknown init", RTLBFS_EINVAL;
-    if (o.tile < 0 || o.tile > 5) return why = "opts.tile out of range", RTLBFS_EINVAL;
+    if (o.tile < 0 || o.tile > 9) return why = "opts.tile out of range", RTLBFS_EINVAL;
     if (o.method != RTLBFS_METHOD_RTLBFS && o.method != RTLBFS_METHOD_TLBFS)
         return why = "unknown opts.method", RTLBFS_EINVAL;
     return RTLBFS_OK;

@@ -23,8 +23,8 @@ using namespace rtlbfs::host;
 
 // ----------------------------------------------------------------- kernels --
 
-template <typename R, bool DEV, int TX, int TY, bool RES, bool TL>
-__global__ void __launch_bounds__((tile2_threads<TX, TY>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_step2d(Domain d, const R *__restrict__ Uin,
+template <typename R, bool DEV, int TX, int TY, bool RES, bool TL, int NSUB>
+__global__ void __launch_bounds__((tile2_threads<TX, TY, NSUB>())) __attribute__((amdgpu_waves_per_eu(7, 8))) k_step2d(Domain d, const R *__restrict__ Uin,
                                                                     R *__restrict__ Uout, double *__restrict__ parts,
                                                                     const uint32_t *__restrict__ ctr_in,
                                                                     uint32_t *__restrict__ ctr_out) {
@@ -32,8 +32,8 @@ __global__ void __launch_bounds__((tile2_threads<TX, TY>())) __attribute__((amdg
     const int ntx = (d.n[0] + TX - 1) / TX;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % ntx) * TX, j0 = (t / ntx) * TY;
-    tile_step_2d<R, DEV, TX, TY, RES, TL>(d, i0, j0, Uin, Uout, parts + (int64_t)t * kPartials, key);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
+    tile_step_2d<R, DEV, TX, TY, RES, TL, NSUB>(d, i0, j0, Uin, Uout, parts + (int64_t)t * kPartials, key);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + (uint32_t)NSUB;
 }
 
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES, bool TL>
@@ -52,11 +52,14 @@ __global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((
 
 namespace {
 
-// 2D tile shapes the autotuner chooses from (opts.tile = index + 1).
+// 2D launch shapes the autotuner chooses from (opts.tile = index + 1): tile
+// size, time steps per launch, and the one-step shape of the same tile (used
+// for an odd last step).
 struct Tile2 {
-    int tx, ty;
+    int tx, ty, nsub, single;
 };
-constexpr Tile2 kTiles2[] = {{32, 8}, {16, 16}, {64, 4}, {16, 8}, {8, 8}};
+constexpr Tile2 kTiles2[] = {{32, 8, 1, 0},  {16, 16, 1, 1}, {64, 4, 1, 2}, {16, 8, 1, 3}, {8, 8, 1, 4},
+                             {16, 16, 2, 1}, {32, 8, 2, 0},  {16, 8, 2, 3}, {8, 8, 2, 4}};
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
 constexpr int kTX2 = 32, kTY2 = 8;             // largest 2D tile (sizes the partials buffer)
 constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per face)
@@ -118,7 +121,7 @@ struct rtlbfs_handle {
     bool own_ws = false;
     int cur = 0;  // which ping-pong copy holds the state
     int tile = 0; // index into kTiles2 (2D)
-    float tune_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // autotuner timings per tile (ms per step)
+    float tune_ms[kNumTiles2] = {};  // autotuner timings per launch shape (ms per step)
     int64_t steps = 0;
     int64_t since_fix = 0;
     bool res_valid = false;
@@ -210,13 +213,13 @@ int read_stored(rtlbfs_t h, int k, std::vector<double> &out) {
     return RTLBFS_OK;
 }
 
-template <typename R, bool DEV, int TX, int TY, bool TL>
+template <typename R, bool DEV, int TX, int TY, bool TL, int NSUB>
 hipError_t launch_step2d(const Domain &d, const R *Uin, R *Uout, double *parts, const uint32_t *ci, uint32_t *co,
                          bool res, hipStream_t s) {
     const int nb = ((d.n[0] + TX - 1) / TX) * ((d.n[1] + TY - 1) / TY);
-    constexpr int nt = tile2_threads<TX, TY>();
-    if (res) k_step2d<R, DEV, TX, TY, true, TL><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
-    else k_step2d<R, DEV, TX, TY, false, TL><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
+    constexpr int nt = tile2_threads<TX, TY, NSUB>();
+    if (res) k_step2d<R, DEV, TX, TY, true, TL, NSUB><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
+    else k_step2d<R, DEV, TX, TY, false, TL, NSUB><<<nb, nt, 0, s>>>(d, Uin, Uout, parts, ci, co);
     return hipGetLastError();
 }
 
@@ -228,12 +231,17 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     const uint32_t *ci = h->ctr() + src;
     uint32_t *co = h->ctr() + (src ^ 1);
     if (d.dim == 2) {
+        double *P = h->parts();
         switch (tile) {
-            case 0: return launch_step2d<R, DEV, 32, 8, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            case 1: return launch_step2d<R, DEV, 16, 16, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            case 2: return launch_step2d<R, DEV, 64, 4, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            case 3: return launch_step2d<R, DEV, 16, 8, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
-            default: return launch_step2d<R, DEV, 8, 8, TL>(d, Uin, Uout, h->parts(), ci, co, res, s);
+            case 0: return launch_step2d<R, DEV, 32, 8, TL, 1>(d, Uin, Uout, P, ci, co, res, s);
+            case 1: return launch_step2d<R, DEV, 16, 16, TL, 1>(d, Uin, Uout, P, ci, co, res, s);
+            case 2: return launch_step2d<R, DEV, 64, 4, TL, 1>(d, Uin, Uout, P, ci, co, res, s);
+            case 3: return launch_step2d<R, DEV, 16, 8, TL, 1>(d, Uin, Uout, P, ci, co, res, s);
+            case 4: return launch_step2d<R, DEV, 8, 8, TL, 1>(d, Uin, Uout, P, ci, co, res, s);
+            case 5: return launch_step2d<R, DEV, 16, 16, TL, 2>(d, Uin, Uout, P, ci, co, res, s);
+            case 6: return launch_step2d<R, DEV, 32, 8, TL, 2>(d, Uin, Uout, P, ci, co, res, s);
+            case 7: return launch_step2d<R, DEV, 16, 8, TL, 2>(d, Uin, Uout, P, ci, co, res, s);
+            default: return launch_step2d<R, DEV, 8, 8, TL, 2>(d, Uin, Uout, P, ci, co, res, s);
         }
     }
     const int grid = ((d.n[0] + kTX3 - 1) / kTX3) * ((d.n[1] + kTY3 - 1) / kTY3) * ((d.n[2] + kTZ3 - 1) / kTZ3);
@@ -259,15 +267,31 @@ hipError_t launch_any(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     }
 }
 
-hipError_t enqueue_step(rtlbfs_t h, bool res, hipStream_t s) {
-    hipError_t e = launch_any(h, h->tile, h->cur, res, s);
-    if (e != hipSuccess) return e;
-    h->cur ^= 1;
-    if (res) {
-        k_finalize_sum<kPartials><<<1, 256, 0, s>>>(h->parts(), step_blocks(h->mesh, h->tile), h->res_out());
-        e = hipGetLastError();
+// Launches that advance n steps with the handle's launch shape: two-step
+// launches while two or more steps remain, then the one-step shape of the
+// same tile.  The Eq. 65 partials are taken on the last step when res.
+int launches_for(const rtlbfs_t h, int64_t n) {
+    const int ns = h->mesh.dim == 2 ? kTiles2[h->tile].nsub : 1;
+    return (int)(n / ns + n % ns);
+}
+
+hipError_t enqueue_steps(rtlbfs_t h, int64_t n, bool res, hipStream_t s) {
+    const int ns = h->mesh.dim == 2 ? kTiles2[h->tile].nsub : 1;
+    while (n > 0) {
+        const int tile = (h->mesh.dim == 2 && n < ns) ? kTiles2[h->tile].single : h->tile;
+        const int64_t adv = n < ns ? 1 : ns;
+        const bool last = n == adv;
+        hipError_t e = launch_any(h, tile, h->cur, res && last, s);
+        if (e != hipSuccess) return e;
+        h->cur ^= 1;
+        if (res && last) {
+            k_finalize_sum<kPartials><<<1, 256, 0, s>>>(h->parts(), step_blocks(h->mesh, tile), h->res_out());
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        n -= adv;
     }
-    return e;
+    return hipSuccess;
 }
 
 hipError_t enqueue_integrals(rtlbfs_t h, double *out, hipStream_t s) {
@@ -296,8 +320,8 @@ hipError_t enqueue_mass_fix(rtlbfs_t h, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Autotuner: time every 2D tile shape on the live state and keep the
-// fastest.  Each trial writes only the spare copy, so the state is unchanged.
+// Autotuner: time every 2D launch shape (tile size, steps per launch) on the
+// live state and keep the fastest per step.  Each trial writes only the spare copy, so the state is unchanged.
 // The launches of one tile are replayed from a captured graph (direct
 // launches of a few-microsecond kernel would time the host's launch rate),
 // and the tiles are timed in interleaved rounds, keeping each tile's best
@@ -338,7 +362,7 @@ int autotune_tile(rtlbfs_t h) {
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess) best_ms[t] = std::min(best_ms[t], ms / kLaunches);
+            if (e == hipSuccess) best_ms[t] = std::min(best_ms[t], ms / (kLaunches * kTiles2[t].nsub));
         }
     }
     if (e != hipSuccess) rc = hip_fail(h, e, "tile autotuning");
@@ -359,8 +383,7 @@ int capture_graph(rtlbfs_t h, int par, int len) {
     h->cur = par;
     hipGraph_t g = nullptr;
     HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < len && e == hipSuccess; ++k) e = enqueue_step(h, k == len - 1, h->cap_stream);
+    hipError_t e = enqueue_steps(h, len, true, h->cap_stream);
     hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     h->cur = saved;
     if (e != hipSuccess) return hip_fail(h, e, "step launch during capture");
@@ -552,12 +575,10 @@ int rtlbfs_step(rtlbfs_t h, int64_t n) {
                 if (rc != RTLBFS_OK) return rc;
             }
             HIP_TRY(h, hipGraphLaunch(h->graph[h->cur], h->stream));
-            if (C & 1) h->cur ^= 1;
+            if (launches_for(h, C) & 1) h->cur ^= 1;
         } else {
-            for (int64_t k = 0; k < chunk; ++k) {
-                hipError_t e = enqueue_step(h, k == chunk - 1, h->stream);
-                if (e != hipSuccess) return hip_fail(h, e, "step launch");
-            }
+            hipError_t e = enqueue_steps(h, chunk, true, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "step launch");
         }
         n -= chunk;
         h->steps += chunk;
@@ -698,15 +719,17 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
     out->dt = h->dom.dt;
     for (int a = 0; a < 3; ++a) out->length[a] = a < h->mesh.dim ? h->length[a] : 1.0;
     out->precision = h->opts.precision;
-    for (int t = 0; t < 8; ++t) out->tune_ms[t] = h->tune_ms[t];
+    for (int t = 0; t < kNumTiles2; ++t) out->tune_ms[t] = h->tune_ms[t];
     if (h->mesh.dim == 2) {
         out->tile_x = kTiles2[h->tile].tx;
         out->tile_y = kTiles2[h->tile].ty;
+        out->steps_per_launch = kTiles2[h->tile].nsub;
         out->tile_z = 1;
     } else {
         out->tile_x = kTX3;
         out->tile_y = kTY3;
         out->tile_z = kTZ3;
+        out->steps_per_launch = 1;
     }
     return RTLBFS_OK;
 }

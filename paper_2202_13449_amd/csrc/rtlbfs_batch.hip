@@ -533,6 +533,7 @@ int rtlbfs_batch_get_info(rtlbfs_batch_t h, int member, rtlbfs_info *out) {
     out->tile_x = kBTX;
     out->tile_y = kBTY;
     out->tile_z = 1;
+    out->steps_per_launch = 1;
     return RTLBFS_OK;
 }
 

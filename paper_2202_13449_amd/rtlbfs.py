@@ -74,7 +74,8 @@ class Info(C.Structure):
         ("tile_x", C.c_int),
         ("tile_y", C.c_int),
         ("tile_z", C.c_int),
-        ("tune_ms", C.c_double * 8),
+        ("tune_ms", C.c_double * 16),
+        ("steps_per_launch", C.c_int),
     ]
 
 

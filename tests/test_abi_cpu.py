@@ -102,7 +102,7 @@ def test_create_rejects_invalid_problems_before_touching_the_device(case):
     elif case == "method":
         opts = rt.make_opts(method=2)
     elif case == "tile":
-        opts = rt.make_opts(tile=6)
+        opts = rt.make_opts(tile=10)
     rc, h = _create(mesh, bc, Ra, Pr, Ma, opts)
     assert rc == rt.EINVAL and not h.value
 

@@ -159,24 +159,51 @@ def test_graph_replay_equals_direct_launches():
     b.step(37)
     for f in range(4):
         assert np.array_equal(a.stored(f), b.stored(f))
+    # two steps per launch: odd chunks (residual_every = 25) replayed from
+    # graphs and launched directly
+    c = rt.Solver(*args, Ra=1e5, noise_amp=1e-3, seed=2, residual_every=25, graph_steps=0, tile=6)
+    e = rt.Solver(*args, Ra=1e5, noise_amp=1e-3, seed=2, residual_every=25, graph_steps=-1, tile=6)
+    r = rt.Solver(*args, Ra=1e5, noise_amp=1e-3, seed=2, residual_every=25, graph_steps=0, tile=1)
+    for n in (50, 50, 37, 1, 25):
+        for x in (c, e, r):
+            x.step(n)
+        assert c.residual() == e.residual()
+        # the FP64 partial sums are reduced in a different order (other block size)
+        assert np.allclose(c.residual(), r.residual(), rtol=1e-13, atol=0)
+        for f in range(4):
+            assert np.array_equal(c.stored(f), e.stored(f))
+            assert np.array_equal(c.stored(f), r.stored(f))
 
 
 def test_every_tile_shape_gives_the_same_state():
-    """The per-cell arithmetic does not depend on the tile shape: all 2D tiles
-    (and the autotuned choice) produce bit-identical states."""
-    args = (2, (70, 45), (1.5, 1.5), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"])
-    ref = None
-    for tile in range(0, 6):
-        s = rt.Solver(*args, Ra=1e5, noise_amp=1e-3, seed=4, tile=tile, precision=rt.FP32_DEV)
-        if tile == 0:
-            tm = list(s.info.tune_ms)[:5]
-            assert all(t > 0 for t in tm), tm
-        s.step(120)
-        st = [s.stored(f) for f in range(4)]
-        if ref is None:
-            ref = st
-        for f in range(4):
-            assert np.array_equal(st[f], ref[f]), (tile, f)
+    """The per-cell arithmetic does not depend on the launch shape: all 2D
+    tiles, one or two steps per launch (the two-step launches recompute the
+    halo ring of their first step), and the autotuned choice produce
+    bit-identical states, in FP32 with stochastic rounding and in FP64, on a
+    walled and on a periodic box, also for step counts the two-step shapes
+    must finish with a one-step launch."""
+    cases = [((2, (70, 45), (1.5, 1.5), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"]), dict(Ra=1e5)),
+             ((2, (52, 20), (0.0, 0.0), (0, 0, 1, 1), (0.0, 0.0, 0.5, -0.5), 1),
+              dict(Ra=1e6, init=INIT_CONDUCTION))]
+    for args, kw in cases:
+        for prec in (rt.FP32_DEV, rt.FP64_PLAIN):
+            ref = None
+            for tile in range(0, 10):
+                s = rt.Solver(*args, noise_amp=1e-3, seed=4, tile=tile, precision=prec, residual_every=20, **kw)
+                if tile == 0:
+                    tm = list(s.info.tune_ms)[:9]
+                    assert all(t > 0 for t in tm), tm
+                assert s.info.steps_per_launch == (2 if tile >= 6 else 1 if tile >= 1 else s.info.steps_per_launch)
+                s.step(120)
+                s.step(7)  # odd: ends with a one-step launch on the two-step shapes
+                st = [s.stored(f) for f in range(4)]
+                res = s.residual()
+                if ref is None:
+                    ref = (st, res)
+                for f in range(4):
+                    assert np.array_equal(st[f], ref[0][f]), (prec, tile, f)
+                # same state; the Eq. 65 sums only differ in reduction order
+                assert np.allclose(res, ref[1], rtol=1e-13, atol=0), (prec, tile, res, ref[1])
 
 
 def test_rest_state_bitwise_and_mass_conservation_on_gpu():
