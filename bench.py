@@ -141,7 +141,7 @@ def time_path(rt, torch, precision, steps, warmup):
     return dict(solver=s, event_ms=ms, wall_s=wall, nu=nu, res=res)
 
 
-def batch_bench(rt, torch, steps, warmup):
+def batch_bench(rt, torch, steps, warmup, sequential=True):
     """256 seeded cavities (sides 64..512, Ra 1e3..1e7, Pr 0.71/7, uniform or
     tanh): the batched handle (one launch per step over all members) against
     the same 256 problems stepped as separate single-domain handles."""
@@ -166,6 +166,14 @@ def batch_bench(rt, torch, steps, warmup):
     ms_batch = e0.elapsed_time(e1) / steps
     del b
     torch.cuda.empty_cache()
+    bpl = BYTES_PER_CELL["f32"] * cells
+    out = {"metric": "cell-updates/s", "workload": "256 batched 2D cavities (seed 4), FP32 deviation",
+           "cells": cells, "steps": steps, "warmup": warmup,
+           "batched": {"ms_per_step": ms_batch, "value": cells / (ms_batch * 1e-3),
+                       "hbm_gbs": bpl / (ms_batch * 1e-3) / 1e9,
+                       "frac": bpl / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    if not sequential:
+        return out
     singles = [rt.Solver(2, (m["n"], m["n"]), (m["stretch"], m["stretch"]), CAVITY_KIND, CAVITY_TDEV,
                          CAVITY_GRAVITY, Ra=m["Ra"], Pr=m["Pr"], Ma=MA, precision=rt.FP32_DEV, seed=4,
                          noise_amp=1e-6, residual_every=100, mass_fix_every=1000) for m in members]
@@ -179,15 +187,9 @@ def batch_bench(rt, torch, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_seq = e0.elapsed_time(e1) / seq_steps
-    bpl = BYTES_PER_CELL["f32"] * cells
-    return {"metric": "cell-updates/s", "workload": "256 batched 2D cavities (seed 4), FP32 deviation",
-            "cells": cells, "steps": steps, "warmup": warmup,
-            "batched": {"ms_per_step": ms_batch, "value": cells / (ms_batch * 1e-3),
-                        "hbm_gbs": bpl / (ms_batch * 1e-3) / 1e9,
-                        "frac": bpl / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS},
-            "sequential_256_handles": {"ms_per_step": ms_seq, "value": cells / (ms_seq * 1e-3),
-                                       "steps": seq_steps},
-            "speedup_batched_vs_sequential": ms_seq / ms_batch}
+    out["sequential_256_handles"] = {"ms_per_step": ms_seq, "value": cells / (ms_seq * 1e-3), "steps": seq_steps}
+    out["speedup_batched_vs_sequential"] = ms_seq / ms_batch
+    return out
 
 
 def timed(torch, solver, steps):
@@ -519,6 +521,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 path (profiling runs)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="with --batch: skip the 256 single-domain handles (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
     ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods",
@@ -551,7 +555,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
         return
     if args.batch:
-        print(json.dumps(batch_bench(rt, torch, args.steps, args.warmup)), flush=True)
+        print(json.dumps(batch_bench(rt, torch, args.steps, args.warmup, sequential=not args.no_sequential)),
+              flush=True)
         return
     if args.workload != "cavity256":
         fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,

@@ -26,7 +26,7 @@ using namespace rtlbfs::host;
 
 namespace {
 
-constexpr int kBTX = 32, kBTY = 8;  // batch tile
+constexpr int kBTX = 16, kBTY = 8;  // batch tile (the fastest of 32x8, 16x16, 64x4, 16x8, 8x8, 16x4 on the 256-cavity batch)
 constexpr int kBRedBlocks = 512;
 
 template <typename R, bool DEV, bool RES, bool TL>
