@@ -141,6 +141,28 @@ def time_path(rt, torch, precision, steps, warmup):
     return dict(solver=s, event_ms=ms, wall_s=wall, nu=nu, res=res)
 
 
+def field_comparison(s32, s64):
+    """Both runs after the same number of steps: velocity maxima (u on the
+    vertical mid-line x = L/2, v on the horizontal mid-line y = L/2, as in
+    Table 1, scaled by L/chi) and the relative L2 error of the FP32 velocity
+    and temperature fields against FP64."""
+    n = N_CELLS_SIDE
+    h = n // 2
+    L, chi = s64.info.L, s64.info.chi
+    out = {}
+    for name, s in (("fp32", s32), ("fp64", s64)):
+        u = s.field(1).reshape(n, n)
+        v = s.field(2).reshape(n, n)
+        out[name] = {"u_max_L_over_chi": float(0.5 * (u[:, h - 1] + u[:, h]).max() * L / chi),
+                     "v_max_L_over_chi": float(0.5 * (v[h - 1, :] + v[h, :]).max() * L / chi)}
+    vel32 = np.stack([s32.field(1), s32.field(2)])
+    vel64 = np.stack([s64.field(1), s64.field(2)])
+    T32, T64 = s32.field(3), s64.field(3)
+    out["rel_l2_velocity"] = float(np.linalg.norm(vel32 - vel64) / np.linalg.norm(vel64))
+    out["rel_l2_temperature"] = float(np.linalg.norm(T32 - T64) / np.linalg.norm(T64))
+    return out
+
+
 def batch_bench(rt, torch, steps, warmup, sequential=True):
     """256 seeded cavities (sides 64..512, Ra 1e3..1e7, Pr 0.71/7, uniform or
     tanh): the batched handle (one launch per step over all members) against
@@ -164,14 +186,27 @@ def batch_bench(rt, torch, steps, warmup, sequential=True):
     torch.cuda.synchronize()
     b.sync()
     ms_batch = e0.elapsed_time(e1) / steps
+    nu32 = [b.nusselt(k)["hot_avg"] for k in range(len(members))]
     del b
     torch.cuda.empty_cache()
+    # the same batch in FP64 plain storage for the same number of steps: the
+    # FP32 members' wall Nusselt numbers against FP64
+    b64 = rt.Batch(meshes, [m["Ra"] for m in members], [m["Pr"] for m in members], bcs, Ma=MA,
+                   precision=rt.FP64_PLAIN, seed=4, noise_amp=1e-6, residual_every=100)
+    b64.step(warmup + steps)
+    nu64 = [b64.nusselt(k)["hot_avg"] for k in range(len(members))]
+    del b64
+    torch.cuda.empty_cache()
+    nu_err = [abs(a - c) / abs(c) for a, c in zip(nu32, nu64)]
     bpl = BYTES_PER_CELL["f32"] * cells
     out = {"metric": "cell-updates/s", "workload": "256 batched 2D cavities (seed 4), FP32 deviation",
            "cells": cells, "steps": steps, "warmup": warmup,
            "batched": {"ms_per_step": ms_batch, "value": cells / (ms_batch * 1e-3),
                        "hbm_gbs": bpl / (ms_batch * 1e-3) / 1e9,
-                       "frac": bpl / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+                       "frac": bpl / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS},
+           "nu_hot_rel_diff_fp32_vs_fp64": {"max": max(nu_err), "median": float(np.median(nu_err)),
+                                            "members_above_1e-4": int(sum(e > 1e-4 for e in nu_err)),
+                                            "steps": warmup + steps}}
     if not sequential:
         return out
     singles = [rt.Solver(2, (m["n"], m["n"]), (m["stretch"], m["stretch"]), CAVITY_KIND, CAVITY_TDEV,
@@ -616,6 +651,7 @@ def main():
         out["nu_rel_diff_fp32_vs_fp64"] = {k: abs(r32["nu"][k] - r64["nu"][k]) / abs(r64["nu"][k])
                                            for k in r64["nu"]}
         out["speedup_fp32_vs_fp64"] = ms64 / ms32
+        out["fields_fp32_vs_fp64"] = field_comparison(r32["solver"], r64["solver"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
