@@ -572,7 +572,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the RTLBFS step of one domain runs on a single MI355X; "
-              "multi-GPU sharding is not part of this build (use --gpus 1)", file=sys.stderr)
+              "multi-GPU sharding is not implemented (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -49,7 +49,7 @@ extern "C" {
 #define RTLBFS_ENOMEM (-2)       /* device allocation failed or workspace too small */
 #define RTLBFS_EDEVICE (-3)      /* a HIP call failed (text in rtlbfs_last_error) */
 #define RTLBFS_EDIVERGED (-4)    /* NaN/Inf or local Mach > 0.5 seen at a residual step */
-#define RTLBFS_EUNSUPPORTED (-5) /* valid request this build does not implement */
+#define RTLBFS_EUNSUPPORTED (-5) /* valid request the library does not implement */
 #define RTLBFS_ESTATE (-6)       /* call order (e.g. a residual before any residual step) */
 
 /* Boundary kinds per side (x-, x+, y-, y+, z-, z+). */

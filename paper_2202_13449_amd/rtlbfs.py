@@ -94,7 +94,7 @@ def load_library() -> C.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2202_13449_amd/build.py`")
     # torch must load its HIP runtime first: the library then binds to that
     # same runtime (same SONAME), so device pointers and streams are shared.
     import torch  # noqa: F401
