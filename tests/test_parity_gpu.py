@@ -362,6 +362,23 @@ def test_tlbfs_fp64_3d_cavity_parity(prec):
     assert max(field_rel(s, o, 3)) <= 1e-11
 
 
+def test_tlbfs_two_step_launches_equal_one_step_launches():
+    """TLBFS through the two-step launch shapes gives the same bits as through
+    the one-step ones (FP32 with stochastic rounding and FP64 deviation)."""
+    args = (2, (52, 36), (1.5, 1.5), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"])
+    for prec in (rt.FP32_DEV, rt.FP64_DEV):
+        ref = None
+        for tile in (2, 6, 7, 9):  # 16x16/1, 16x16/2, 32x8/2, 8x8/2
+            s = rt.Solver(*args, Ra=1e5, noise_amp=1e-3, seed=6, tile=tile, precision=prec,
+                          method=rt.METHOD_TLBFS, residual_every=30)
+            s.step(91)
+            st = [s.stored(f) for f in range(4)]
+            if ref is None:
+                ref = st
+            for f in range(4):
+                assert np.array_equal(st[f], ref[f]), (prec, tile, f)
+
+
 def test_tlbfs_fp32_short_horizon_and_tiles():
     """FP32 deviation TLBFS against the FP64 oracle over a short horizon, and
     every tile shape gives the same state."""
