@@ -26,12 +26,12 @@ FP64_TOL = 1e-12
 
 def make_pair(dim, n, stretch, kind, Tdev, gaxis, Ra=1e4, Pr=0.71, Ma=0.1, precision=rt.FP64_PLAIN, seed=1,
               noise=1e-3, init=INIT_REST, dtl=1.0, dt=0.0, residual_every=100, graph_steps=0, L_axis=None,
-              method=rt.METHOD_RTLBFS):
+              method=rt.METHOD_RTLBFS, tile=0):
     """A GPU solver and an oracle run of the same problem (the oracle is given
     the parameters the library derived, read back through rtlbfs_get_info)."""
     s = rt.Solver(dim, n, stretch, kind, Tdev, gaxis, Ra=Ra, Pr=Pr, Ma=Ma, precision=precision, seed=seed,
                   noise_amp=noise, init=init, dtl=dtl, dt=dt, residual_every=residual_every,
-                  graph_steps=graph_steps, method=method)
+                  graph_steps=graph_steps, method=method, tile=tile)
     info = s.info
     # independent derivation of Eq. 63 on the oracle side
     La = info.L
@@ -226,15 +226,45 @@ def test_minimum_mesh_and_single_tile():
     assert max(field_rel(s, o, 2)) <= FP64_TOL
 
 
-def test_c2_full_size_prefix_fp64():
+@pytest.mark.parametrize("tile", [0, 6])
+def test_c2_full_size_prefix_fp64(tile):
     """256^2 tanh (phi = 1.5) cavity at Ra = 1e6, the benchmarked
-    configuration, in the benchmarked launch configuration: 100 steps
-    compared cell by cell with the oracle."""
-    s, o = make_pair(2, (256, 256), (1.5, 1.5), **DHC2, Ra=1e6, noise=1e-6)
+    configuration, in the autotuned launch shape and in 16x16 with two steps
+    per launch: 100 steps compared cell by cell with the oracle."""
+    s, o = make_pair(2, (256, 256), (1.5, 1.5), **DHC2, Ra=1e6, noise=1e-6, tile=tile)
     s.step(100)
     o.step(100)
     rel = field_rel(s, o, 2)
     assert max(rel) <= FP64_TOL, rel
+
+
+_FULL_SIZE_ORACLE = {}
+
+
+@pytest.mark.parametrize("tile", [0, 6])
+def test_c2_full_size_fp32_in_the_benchmarked_configuration(tile):
+    """The benchmark workload itself: 256^2 tanh cavity, Ra = 1e6, FP32
+    deviation storage with stochastic rounding, 200 steps against the FP64
+    oracle cell by cell; in the autotuned launch shape and in 16x16 with two
+    steps per launch (the shape the autotuner usually picks on this size).
+    Besides the usual scale (V_c for velocities), every field is held to its
+    own maximum, since the flow is still weak this early."""
+    s, o = make_pair(2, (256, 256), (1.5, 1.5), **DHC2, Ra=1e6, noise=1e-6, precision=rt.FP32_DEV, tile=tile)
+    if tile == 6:
+        assert (s.info.tile_x, s.info.tile_y, s.info.steps_per_launch) == (16, 16, 2)
+    s.step(200)
+    if "fp32" not in _FULL_SIZE_ORACLE:  # the oracle run does not depend on the launch shape
+        o.step(200)
+        _FULL_SIZE_ORACLE["fp32"] = o
+    o = _FULL_SIZE_ORACLE["fp32"]
+    rel = field_rel(s, o, 2)
+    own = [float(np.abs(s.field(f) - o.prim(f)).max() / np.abs(o.prim(f)).max()) for f in (1, 2, 3)]
+    r_gpu, r_orc = s.stored(0), o.stored(0)
+    r_rel = float(np.abs(r_gpu - r_orc).max() / np.abs(r_orc).max())
+    print("tile", (s.info.tile_x, s.info.tile_y, s.info.steps_per_launch), "r", r_rel, "rel", rel, "own", own)
+    assert r_rel <= 1e-5
+    assert max(rel[1:]) <= 1e-4, rel
+    assert max(own) <= 1e-5, own  # measured: about 4e-7
 
 
 # ------------------------------------------------------------- 3D --------
