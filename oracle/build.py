@@ -10,12 +10,13 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rtlbfs_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "curv_oracle.c")]
 LIB = os.path.join(HERE, "librtlbfs_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-           "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+           "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

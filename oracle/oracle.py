@@ -13,7 +13,7 @@ from typing import Sequence
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB, SRCS, build
 
 PERIODIC, WALL_ISOTHERMAL, WALL_ADIABATIC = 0, 1, 2
 INIT_REST, INIT_CONDUCTION = 0, 1
@@ -49,8 +49,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    src = os.path.join(os.path.dirname(LIB), "rtlbfs_oracle.c")
-    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(src):
+    newest = max(os.path.getmtime(f) for f in SRCS + [f[:-2] + ".h" for f in SRCS])
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
         build()
     lib = C.CDLL(LIB)
     D, P, I, L = C.c_double, C.POINTER(C.c_double), C.c_int, C.c_long
@@ -80,6 +80,7 @@ def _load():
     lib.orc_integrals.argtypes = [VP, P]
     lib.orc_taus.argtypes = [VP, P]
     lib.orc_face_flux.argtypes = [C.POINTER(_Cfg), I, P, P, P, P, D, D, P, P]
+    lib.orc_face_flux_frame.argtypes = [C.POINTER(_Cfg), P, P, P, P, P, P, P, D, P, P]
     _lib = lib
     return lib
 
@@ -165,6 +166,29 @@ def face_flux(cfg: OracleConfig, axis: int, primL, gradL, primR, gradR, dL: floa
     flux = np.zeros(D + 2)
     pred = np.zeros(D + 2)
     lib.orc_face_flux(C.byref(c), axis, _ptr(pL), _ptr(gL), _ptr(pR), _ptr(gR), dL, dR, _ptr(flux), _ptr(pred))
+    return flux, pred
+
+
+def face_flux_frame(cfg: OracleConfig, primL, gradL, primR, gradR, xSL, xSR, fdir, Tb: float):
+    """The interior-face flux in its own frame (axis 0 = face normal): grad
+    arrays (D+2, D), offsets xSL = x_S - x_L and xSR = x_S - x_R, buoyancy
+    direction fdir, absolute buoyancy reference Tb.  Returns (flux, pred)."""
+    lib = _load()
+    c = cfg.to_c()
+    D = cfg.dim
+    vec = lambda v: np.concatenate([np.asarray(v, dtype=np.float64).reshape(-1), np.zeros(3)])[:3].copy()
+    pL = np.ascontiguousarray(primL, dtype=np.float64)
+    pR = np.ascontiguousarray(primR, dtype=np.float64)
+    gL = np.zeros((D + 2, 3))
+    gR = np.zeros((D + 2, 3))
+    aL = np.asarray(gradL, dtype=np.float64).reshape(D + 2, -1)
+    aR = np.asarray(gradR, dtype=np.float64).reshape(D + 2, -1)
+    gL[:, :aL.shape[1]] = aL
+    gR[:, :aR.shape[1]] = aR
+    flux = np.zeros(D + 2)
+    pred = np.zeros(D + 2)
+    lib.orc_face_flux_frame(C.byref(c), _ptr(pL), _ptr(gL), _ptr(pR), _ptr(gR), _ptr(vec(xSL)), _ptr(vec(xSR)),
+                            _ptr(vec(fdir)), Tb, _ptr(flux), _ptr(pred))
     return flux, pred
 
 

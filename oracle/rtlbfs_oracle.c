@@ -179,12 +179,14 @@ static double d2(const nodefield *f, int a, int b, double h)
 }
 
 /* Primitives at every node of the face lattice by Eq. 29.  Node (a, b, c)
- * sits at x_S + h (a n + b t1 + c t2); relative to the left centre that is
- * (dL + a h) along the face normal and (b h, c h) along the tangential axes;
- * relative to the right centre the normal part is (a h - dR).  val[p] is
- * indexed by the local offsets. */
+ * sits at x_S + h (a n + b t1 + c t2), where n is the frame axis `axis` and
+ * t1, t2 the remaining axes in increasing order.  xSL = x_S - x_L and xSR =
+ * x_S - x_R are the face centre relative to the two cell centres (on a
+ * Cartesian mesh dL n and -dR n), so the node lies at xSL + h (a, b, c)
+ * from the left centre and at xSR + h (a, b, c) from the right one.  val[p]
+ * is indexed by the local offsets. */
 static void reconstruct_nodes(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
-                              const double *primR, const double *gradR, double dL, double dR,
+                              const double *primR, const double *gradR, const double *xSL, const double *xSR,
                               nodefield *val)
 {
     const int D = cfg->dim;
@@ -201,14 +203,9 @@ static void reconstruct_nodes(const orc_cfg *cfg, int axis, const double *primL,
                 double rL[3] = {0, 0, 0}, rR[3] = {0, 0, 0};
                 int t = 1;
                 for (int ax = 0; ax < D; ++ax) {
-                    if (ax == axis) {
-                        rL[ax] = dL + a * h;
-                        rR[ax] = a * h - dR;
-                    } else {
-                        rL[ax] = off[t] * h;
-                        rR[ax] = off[t] * h;
-                        ++t;
-                    }
+                    int o = ax == axis ? a : off[t++];
+                    rL[ax] = xSL[ax] + o * h;
+                    rR[ax] = xSR[ax] + o * h;
                 }
                 for (int p = 0; p < NP; ++p) {
                     double vL = primL[p], vR = primR[p];
@@ -225,11 +222,15 @@ static void reconstruct_nodes(const orc_cfg *cfg, int axis, const double *primL,
             }
 }
 
-static void tlbfs_face_flux(const orc_cfg *cfg, int axis, const nodefield *val, double *flux, double *pred);
+static void tlbfs_face_flux(const orc_cfg *cfg, int axis, const nodefield *val, const double *fdir, double Tb,
+                            double *flux, double *pred);
 
-void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
-                   const double *primR, const double *gradR, double dL, double dR,
-                   double *flux, double *pred)
+/* The interior-face flux along +axis of the frame the arguments are given in.
+ * fdir: unit vector of the buoyancy (against gravity) in that frame, or zero;
+ * Tb: the absolute reference temperature of the buoyancy force. */
+static void face_flux_core(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
+                           const double *primR, const double *gradR, const double *xSL, const double *xSR,
+                           const double *fdir, double Tb, double *flux, double *pred)
 {
     const int D = cfg->dim;
     const int dev = cfg->deviation;
@@ -240,9 +241,9 @@ void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const doub
 
     /* Step 1: primitives at the lattice nodes (Eq. 29). */
     nodefield val[5];
-    reconstruct_nodes(cfg, axis, primL, gradL, primR, gradR, dL, dR, val);
+    reconstruct_nodes(cfg, axis, primL, gradL, primR, gradR, xSL, xSR, val);
     if (cfg->method == 1) {
-        tlbfs_face_flux(cfg, axis, val, flux, pred);
+        tlbfs_face_flux(cfg, axis, val, fdir, Tb, flux, pred);
         return;
     }
 
@@ -311,9 +312,11 @@ void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const doub
         for (int y = 0; y < D; ++y) drho += 0.5 * dtl * dtl * d2(&P[x][y], x, y, h);
 
     double force[3] = {0, 0, 0};
-    if (cfg->gravity_axis >= 0 && cfg->force_in_predictor) {
-        double Tabs_minus_ref = dev ? T0n : (T0n - TREF);
-        force[cfg->gravity_axis] = cfg->beta_g * rho0 * Tabs_minus_ref; /* Eq. 64 */
+    if (cfg->force_in_predictor) {
+        /* T - T_b from T' = T - T0 (deviation) or the absolute T */
+        double Tabs_minus_ref = dev ? T0n + (TREF - Tb) : (T0n - Tb);
+        for (int x = 0; x < D; ++x)
+            if (fdir[x] != 0.0) force[x] = fdir[x] * cfg->beta_g * rho0 * Tabs_minus_ref; /* Eq. 64 */
     }
     double dm[3] = {0, 0, 0}; /* (rho u)* - (rho u)_0 */
     for (int x = 0; x < D; ++x) {
@@ -374,6 +377,24 @@ void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const doub
     }
 }
 
+void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const double *gradL,
+                   const double *primR, const double *gradR, double dL, double dR,
+                   double *flux, double *pred)
+{
+    double xSL[3] = {0, 0, 0}, xSR[3] = {0, 0, 0}, fdir[3] = {0, 0, 0};
+    xSL[axis] = dL;
+    xSR[axis] = -dR;
+    if (cfg->gravity_axis >= 0) fdir[cfg->gravity_axis] = 1.0;
+    face_flux_core(cfg, axis, primL, gradL, primR, gradR, xSL, xSR, fdir, TREF, flux, pred);
+}
+
+void orc_face_flux_frame(const orc_cfg *cfg, const double *primL, const double *gradL, const double *primR,
+                         const double *gradR, const double *xSL, const double *xSR, const double *fdir, double Tb,
+                         double *flux, double *pred)
+{
+    face_flux_core(cfg, 0, primL, gradL, primR, gradR, xSL, xSR, fdir, Tb, flux, pred);
+}
+
 /* TLBFS interface flux (Sec. 2.2), in the paper's order:
  *   (a) primitives at x_S - e_i dt by Eq. 29 (the lattice nodes above: node
  *       offset (a, b, c) = -e_i in the face frame), and f_i^eq, g_i^eq there
@@ -387,7 +408,8 @@ void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const doub
  * node values are converted first and the fluxes afterwards (the r flux is the
  * rho flux, the theta flux is Q - T0 P, and the constant pressure c_s^2 is
  * left out of the momentum flux). */
-static void tlbfs_face_flux(const orc_cfg *cfg, int axis, const nodefield *val, double *flux, double *pred)
+static void tlbfs_face_flux(const orc_cfg *cfg, int axis, const nodefield *val, const double *fdir, double Tb,
+                            double *flux, double *pred)
 {
     const int D = cfg->dim;
     const int dev = cfg->deviation;
@@ -446,8 +468,9 @@ static void tlbfs_face_flux(const orc_cfg *cfg, int axis, const nodefield *val, 
         for (int ax = 0; ax < D; ++ax) ms[ax] += e[i][ax] * fb[i];
         Es += gb[i];
     }
-    if (cfg->gravity_axis >= 0 && cfg->force_in_predictor)
-        ms[cfg->gravity_axis] += dtl * cfg->beta_g * rho_c * (T_c - TREF); /* Eq. 64 at the face centre */
+    if (cfg->force_in_predictor)
+        for (int ax = 0; ax < D; ++ax)
+            if (fdir[ax] != 0.0) ms[ax] += fdir[ax] * dtl * cfg->beta_g * rho_c * (T_c - Tb); /* Eq. 64, face centre */
     double us[3] = {0.0, 0.0, 0.0};
     for (int ax = 0; ax < D; ++ax) us[ax] = ms[ax] / rhos;
     double Ts = Es / rhos;

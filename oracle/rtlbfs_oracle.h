@@ -99,6 +99,16 @@ void orc_face_flux(const orc_cfg *cfg, int axis, const double *primL, const doub
                    const double *primR, const double *gradR, double dL, double dR,
                    double *flux, double *pred);
 
+/* The same flux in a frame of its own: axis 0 is the face normal n (from the
+ * left to the right cell), axes 1 (and 2) the tangents; primitives, their
+ * gradients [p*3 + a], xSL = x_S - x_L, xSR = x_S - x_R and the buoyancy
+ * direction fdir (unit vector against gravity, or zero) are all given in that
+ * frame.  Tb is the absolute reference temperature of the buoyancy force.
+ * flux: D+2 values per unit area along +n, momentum in the frame. */
+void orc_face_flux_frame(const orc_cfg *cfg, const double *primL, const double *gradL, const double *primR,
+                         const double *gradR, const double *xSL, const double *xSR, const double *fdir, double Tb,
+                         double *flux, double *pred);
+
 #ifdef __cplusplus
 }
 #endif

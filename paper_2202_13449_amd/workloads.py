@@ -43,3 +43,58 @@ def batch_cavities(count: int = 256, seed: int = 4):
 
 def total_cells(members) -> int:
     return sum(m["n"] * m["n"] for m in members)
+
+
+# ---------------------------------------------------------------- curvilinear
+
+def geometric_radii(n: int, r0: float, r1: float, first: float):
+    """n + 1 radii from r0 to r1 whose spacing starts at `first` and grows by
+    a constant ratio (found by bisection); uniform if first * n equals r1 - r0."""
+    L = r1 - r0
+    if abs(first * n - L) <= 1e-12 * L:
+        return [r0 + L * k / n for k in range(n + 1)]
+
+    def span(q):
+        return first * (q ** n - 1.0) / (q - 1.0)
+
+    lo, hi = (1.0 + 1e-12, 2.0) if first * n < L else (1e-3, 1.0 - 1e-12)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if span(mid) < L:
+            lo = mid
+        else:
+            hi = mid
+    q = 0.5 * (lo + hi)
+    r = [r0 + first * (q ** k - 1.0) / (q - 1.0) for k in range(n + 1)]
+    r[-1] = r1
+    return r
+
+
+def o_mesh(ni: int, nj: int, r_in: float, r_out: float, first: float, theta0: float = 0.0):
+    """Vertices of an O-type mesh between circles of radii r_in and r_out:
+    i runs counter-clockwise around (vertex column ni is column 0 again, so
+    the i sides are periodic), j runs outward with geometric radial spacing
+    that starts at `first`.  Returns x, y as nested lists (nj + 1) x (ni + 1)."""
+    r = geometric_radii(nj, r_in, r_out, first)
+    th = [theta0 + 2.0 * math.pi * (i % ni) / ni for i in range(ni + 1)]
+    x = [[rj * math.cos(t) for t in th] for rj in r]
+    y = [[rj * math.sin(t) for t in th] for rj in r]
+    return x, y
+
+
+# Sec. 4.3: mixed convection from a heated circular cylinder.  O-type mesh of
+# 300 x 450 cells (read here as 450 around the cylinder and 300 outward), far
+# field 52.5 D from the centre, first cell 0.003 D; free stream 0.1 c_s along
+# +y (against gravity: buoyancy aids the flow), T_inf = 0, T_wall = 1,
+# Re = 20, Pr = 0.7, Gr in {0, 100, 800, 1600}.  Lengths in units of the
+# first cell, so D = 1 / 0.003.
+CYLINDER = dict(ni=450, nj=300, far=52.5, first=0.003, Re=20.0, Pr=0.7, Gr=(0.0, 100.0, 800.0, 1600.0),
+                u_inf_cs=0.1, T_wall=1.0, T_inf=0.0)
+
+
+def cylinder_mesh(ni: int = 450, nj: int = 300, far: float = 52.5, first: float = 0.003):
+    """O-mesh of the cylinder of diameter D = 1/first (first cell of unit
+    size) with the far field at `far` * D from the centre.  Returns (x, y, D)."""
+    D = 1.0 / first
+    x, y = o_mesh(ni, nj, 0.5 * D, far * D, 1.0, theta0=-0.5 * math.pi)
+    return x, y, D

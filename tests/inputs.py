@@ -51,3 +51,38 @@ def random_state(N: int, dim: int, seed: int, amp_rho=1e-3, amp_u=0.02, amp_T=0.
     u = amp_u * g.uniform(-1, 1, (dim, N))
     T = 0.5 + amp_T * g.uniform(-1, 1, N)
     return rho, u, T
+
+
+# ------------------------------------------------------ curvilinear meshes --
+
+FARFIELD = 3
+
+
+def cartesian_vertices(xn, yn):
+    """Vertex arrays (nj + 1, ni + 1) of the Cartesian mesh with node
+    coordinates xn along i and yn along j."""
+    X, Y = np.meshgrid(np.asarray(xn, dtype=np.float64), np.asarray(yn, dtype=np.float64))
+    return X.copy(), Y.copy()
+
+
+def rotated(x, y, angle):
+    c, s = np.cos(angle), np.sin(angle)
+    return c * x - s * y, s * x + c * y
+
+
+def wavy_vertices(xn, yn, amp):
+    """A Cartesian mesh bent by smooth sine displacements of relative size
+    `amp`; the outer boundary stays rectangular."""
+    X, Y = cartesian_vertices(xn, yn)
+    Lx, Ly = X.max() - X.min(), Y.max() - Y.min()
+    sx = np.sin(np.pi * (X - X.min()) / Lx)
+    sy = np.sin(np.pi * (Y - Y.min()) / Ly)
+    return X + amp * Lx * sx * sy * np.sin(2 * np.pi * (Y - Y.min()) / Ly), \
+        Y + amp * Ly * sx * sy * np.cos(2 * np.pi * (X - X.min()) / Lx)
+
+
+def o_mesh(ni, nj, r_in, r_out, first, theta0=0.0):
+    from paper_2202_13449_amd.workloads import o_mesh as _o
+
+    x, y = _o(ni, nj, r_in, r_out, first, theta0)
+    return np.array(x), np.array(y)
