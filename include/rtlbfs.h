@@ -219,6 +219,81 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out);
 /* Destroy; frees only what the library allocated.  NULL is a no-op. */
 int rtlbfs_destroy(rtlbfs_t h);
 
+/* ------------------------------------------------- body-fitted 2D meshes -- */
+/* The same step on a 2D structured curvilinear (body-fitted) quadrilateral
+ * mesh, the setting of Secs. 4.3 and 4.5 (O-type meshes around a heated
+ * cylinder and in an annulus).  Every face carries its own unit normal n and
+ * area dS (edge length); the D2Q9 lattice of the predictor is aligned with
+ * (n, t) on each face; cell gradients are the Gauss sums of Eq. 55 over the
+ * four faces with Eq. 56 face values (inverse distances of the face midpoint
+ * from the two cell centroids).  Cell centre = centroid of the quadrilateral.
+ * Walls use the one-sided closure of the Cartesian meshes in the face frame,
+ * with d the normal distance of the centroid from the wall face.
+ *
+ * A far-field side (RTLBFS_FARFIELD) is an ordinary face against a ghost
+ * cell mirrored across it (same normal distance, zero gradient): where the
+ * far-field velocity points into the domain the ghost holds u_inf and T_inf
+ * with the fluid cell's density, elsewhere rho = 1 with the fluid cell's
+ * velocity and temperature.
+ *
+ * Buoyancy: beta_g rho (T - T_ref) along the unit vector `up`, in the cell
+ * update and (unless opts.buoyancy_update_only) in the predicted momentum.
+ * Temperatures here are absolute.  Cells are stored i-fastest: index
+ * = i + ni*j, the field layout of the Cartesian 2D meshes. */
+#define RTLBFS_FARFIELD 3
+
+typedef struct {
+    int n[2];        /* cells along i (n[0]) and j (n[1]); each >= 4 */
+    const double *x; /* host vertex coordinates, (n[1]+1) * (n[0]+1) values, i fastest:
+                        vertex (i, j) at x[j*(n[0]+1) + i]; cell (i, j) has the corners
+                        (i, j), (i+1, j), (i+1, j+1), (i, j+1), all cells with the same
+                        orientation and positive area.  Read during create only. */
+    const double *y;
+} rtlbfs_curv_mesh;
+
+typedef struct {
+    int kind[4];     /* sides i-, i+, j-, j+: RTLBFS_PERIODIC (in pairs; the mesh must close
+                        on itself: vertex column n[0] (row n[1]) equals column (row) 0),
+                        RTLBFS_WALL_ISOTHERMAL, RTLBFS_WALL_ADIABATIC or RTLBFS_FARFIELD */
+    double Tw[4];    /* absolute temperature of isothermal walls */
+    double up[2];    /* unit vector against gravity, or (0, 0) for no buoyancy */
+    double T_ref;    /* absolute reference temperature of the buoyancy force */
+    double u_inf[2]; /* far-field velocity (also the initial velocity) */
+    double T_inf;    /* far-field absolute temperature (also the initial temperature) */
+} rtlbfs_curv_bc;
+
+/* Device workspace for a body-fitted mesh (bytes); 0 for invalid arguments. */
+size_t rtlbfs_curv_workspace_bytes(const rtlbfs_curv_mesh *mesh, const rtlbfs_opts *opts);
+
+/* Create a solver on a body-fitted mesh.  nu, chi, beta_g are given directly
+ * (opts->phys_given and Ra/Pr/Ma do not apply).  The state starts at rho = 1,
+ * u = u_inf, T = T_inf (+ opts->noise_amp noise on T).  Every other option,
+ * the workspace and stream rules and the error codes are those of
+ * rtlbfs_create; opts->tile must be 0 (one 16 x 16 launch shape) and
+ * opts->init is ignored.  The handle works with rtlbfs_step, _sync,
+ * _residual, _integrals, _get_field, _set_state, _get_stored, _get_info and
+ * _destroy; rtlbfs_nusselt returns RTLBFS_EUNSUPPORTED (use
+ * rtlbfs_wall_heat).  EINVAL also for a mesh that folds over or does not
+ * close on a periodic pair. */
+int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, double beta_g,
+                       const rtlbfs_curv_bc *bc, const rtlbfs_opts *opts, void *hip_stream, void *workspace,
+                       size_t ws_bytes, rtlbfs_t *out);
+
+/* Heat through one isothermal side of a body-fitted mesh (synchronising, FP64):
+ * out[0] = sum_k (T_w - T_P,k) / d_k dS_k over the side's faces (the
+ * one-sided wall-normal temperature gradient times the face area, heat into
+ * the fluid per unit chi), out[1] = sum_k dS_k.  Nusselt numbers are formed
+ * from these: Eq. 73 on a cylinder is out[0] / (pi dT), the average of
+ * Eq. 78 on a cylinder of radius R and height H is R out[0] / (out[1] dT)
+ * per unit height.  EINVAL if the side is not an isothermal wall,
+ * EUNSUPPORTED on a Cartesian handle. */
+int rtlbfs_wall_heat(rtlbfs_t h, int side, double out[2]);
+
+/* Geometry the library derived for a body-fitted mesh (host only): cell
+ * centroids and areas, `count` >= cells values each (any pointer may be
+ * NULL).  EUNSUPPORTED on a Cartesian handle. */
+int rtlbfs_curv_cells(rtlbfs_t h, double *host_cx, double *host_cy, double *host_area, size_t count);
+
 /* ----------------------------------------------------------- batched -- */
 /* Many independent 2D domains advanced together: one kernel launch per step
  * covers the tiles of every member, replayed from a captured HIP graph.

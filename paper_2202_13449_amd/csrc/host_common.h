@@ -258,9 +258,10 @@ inline void fill_domain(const Problem &p, int precision, int force_pred, int rou
     ph.inv2h = 1.0 / (2.0 * d.dtl);
     ph.invh2 = 1.0 / (d.dtl * d.dtl);
     ph.inv4h2 = 1.0 / (4.0 * d.dtl * d.dtl);
+    ph.Tref_s = dev ? 0.0 : kT0;  // T_ref = T0 on the Cartesian meshes
     d.phd = ph;
     d.phf = {(float)ph.nu, (float)ph.chi, (float)ph.dtl, (float)ph.tau_f, (float)ph.tau_g, (float)ph.bg,
-             (float)ph.dt, (float)ph.h, (float)ph.inv2h, (float)ph.invh2, (float)ph.inv4h2};
+             (float)ph.dt, (float)ph.h, (float)ph.inv2h, (float)ph.invh2, (float)ph.inv4h2, (float)ph.Tref_s};
     for (int s = 0; s < 6; ++s) d.Twf[s] = (float)d.Tw[s];
 }
 

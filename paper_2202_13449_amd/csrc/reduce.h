@@ -170,10 +170,14 @@ __global__ void __launch_bounds__(256) k_integrals(Domain d, const R *__restrict
     const int64_t N = d.fstride;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < d.cells;
          c += (int64_t)gridDim.x * blockDim.x) {
-        int ijk[3];
-        cell_ijk(d, c, ijk);
         double vol = 1.0;
-        for (int a = 0; a < d.dim; ++a) vol *= d.w[a][ijk[a]];
+        if (d.vol) {
+            vol = d.vol[c];
+        } else {
+            int ijk[3];
+            cell_ijk(d, c, ijk);
+            for (int a = 0; a < d.dim; ++a) vol *= d.w[a][ijk[a]];
+        }
         const double r = (double)U[c];
         const double e = (double)U[(d.dim + 1) * N + c];
         const double rdev = DEV ? r : r - 1.0;

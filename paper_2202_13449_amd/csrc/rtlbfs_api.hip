@@ -17,6 +17,8 @@
 #include "step2d.h"
 #include "step3d.h"
 #include "host_common.h"
+#include "curv2d.h"
+#include "curv_host.h"
 
 using namespace rtlbfs;
 using namespace rtlbfs::host;
@@ -47,6 +49,23 @@ __global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((
     const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
     tile_step_3d<R, DEV, TX, TY, TZ, RES, TL>(d, bx * TX, by * TY, bz * TZ, Uin, Uout,
                                               parts + (int64_t)t * kPartials, key);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
+}
+
+constexpr int kCTX = 16, kCTY = 16;  // tile of the body-fitted step kernel
+
+template <typename R, bool DEV, bool TL, bool RES>
+__global__ void __launch_bounds__((curv_threads<kCTX, kCTY>())) k_curv_step(Domain d, CurvGeo g,
+                                                                          const R *__restrict__ Uin,
+                                                                          R *__restrict__ Uout,
+                                                                          double *__restrict__ parts,
+                                                                          const uint32_t *__restrict__ ctr_in,
+                                                                          uint32_t *__restrict__ ctr_out) {
+    const uint32_t key = *ctr_in;
+    const int ntx = (d.n[0] + kCTX - 1) / kCTX;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    tile_step_curv<R, DEV, TL, kCTX, kCTY, RES>(d, g, (t % ntx) * kCTX, (t / ntx) * kCTY, Uin, Uout,
+                                                parts + (int64_t)t * kPartials, key);
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
@@ -130,6 +149,14 @@ struct rtlbfs_handle {
     int graph_len = 0;
     double *host_buf = nullptr;  // pinned scratch for small reads
     std::string err;
+    // body-fitted mesh (rtlbfs_curv_create)
+    bool curv = false;
+    CurvGeo cg{};
+    const double *fi64 = nullptr, *fj64 = nullptr;  // FP64 face records (diagnostics)
+    int64_t nfi = 0, nfj = 0;
+    int ckind[4] = {0, 0, 0, 0};
+    double cTw[4] = {0, 0, 0, 0};                   // absolute wall temperatures
+    std::vector<double> ccx, ccy, carea;            // host copy of the cell geometry
 
     void *U(int k) { return ws + lay.off_U[k]; }
     double *parts() { return (double *)(ws + lay.off_parts); }
@@ -251,9 +278,37 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     return hipGetLastError();
 }
 
+int curv_blocks(const rtlbfs_mesh &m) { return ((m.n[0] + kCTX - 1) / kCTX) * ((m.n[1] + kCTY - 1) / kCTY); }
+
+// Blocks of one step launch of the handle (rows of residual partials).
+int handle_blocks(const rtlbfs_t h, int tile) { return h->curv ? curv_blocks(h->mesh) : step_blocks(h->mesh, tile); }
+
+template <typename R, bool DEV, bool TL>
+hipError_t launch_curv(rtlbfs_t h, int src, bool res, hipStream_t s) {
+    const R *Uin = (const R *)h->U(src);
+    R *Uout = (R *)h->U(src ^ 1);
+    const uint32_t *ci = h->ctr() + src;
+    uint32_t *co = h->ctr() + (src ^ 1);
+    const int nb = curv_blocks(h->mesh);
+    constexpr int nt = curv_threads<kCTX, kCTY>();
+    if (res) k_curv_step<R, DEV, TL, true><<<nb, nt, 0, s>>>(h->dom, h->cg, Uin, Uout, h->parts(), ci, co);
+    else k_curv_step<R, DEV, TL, false><<<nb, nt, 0, s>>>(h->dom, h->cg, Uin, Uout, h->parts(), ci, co);
+    return hipGetLastError();
+}
+
 // One step kernel from copy `src` into the other copy (no state change on the host side).
 hipError_t launch_any(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     const bool tl = h->opts.method == RTLBFS_METHOD_TLBFS;
+    if (h->curv) {
+        switch (h->opts.precision) {
+            case RTLBFS_FP64_PLAIN:
+                return tl ? launch_curv<double, false, true>(h, src, res, s) : launch_curv<double, false, false>(h, src, res, s);
+            case RTLBFS_FP64_DEV:
+                return tl ? launch_curv<double, true, true>(h, src, res, s) : launch_curv<double, true, false>(h, src, res, s);
+            default:
+                return tl ? launch_curv<float, true, true>(h, src, res, s) : launch_curv<float, true, false>(h, src, res, s);
+        }
+    }
     switch (h->opts.precision) {
         case RTLBFS_FP64_PLAIN:
             return tl ? launch_step<double, false, true>(h, tile, src, res, s)
@@ -271,12 +326,12 @@ hipError_t launch_any(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
 // launches while two or more steps remain, then the one-step shape of the
 // same tile.  The Eq. 65 partials are taken on the last step when res.
 int launches_for(const rtlbfs_t h, int64_t n) {
-    const int ns = h->mesh.dim == 2 ? kTiles2[h->tile].nsub : 1;
+    const int ns = (h->mesh.dim == 2 && !h->curv) ? kTiles2[h->tile].nsub : 1;
     return (int)(n / ns + n % ns);
 }
 
 hipError_t enqueue_steps(rtlbfs_t h, int64_t n, bool res, hipStream_t s) {
-    const int ns = h->mesh.dim == 2 ? kTiles2[h->tile].nsub : 1;
+    const int ns = (h->mesh.dim == 2 && !h->curv) ? kTiles2[h->tile].nsub : 1;
     while (n > 0) {
         const int tile = (h->mesh.dim == 2 && n < ns) ? kTiles2[h->tile].single : h->tile;
         const int64_t adv = n < ns ? 1 : ns;
@@ -285,7 +340,7 @@ hipError_t enqueue_steps(rtlbfs_t h, int64_t n, bool res, hipStream_t s) {
         if (e != hipSuccess) return e;
         h->cur ^= 1;
         if (res && last) {
-            k_finalize_sum<kPartials><<<1, 256, 0, s>>>(h->parts(), step_blocks(h->mesh, tile), h->res_out());
+            k_finalize_sum<kPartials><<<1, 256, 0, s>>>(h->parts(), handle_blocks(h, tile), h->res_out());
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -392,6 +447,66 @@ int capture_graph(rtlbfs_t h, int par, int len) {
     (void)hipGraphDestroy(g);
     if (e3 != hipSuccess) return hip_fail(h, e3, "hipGraphInstantiate");
     return RTLBFS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Workspace of a body-fitted mesh: two state copies, face records and 1/dV in
+// the kernel precision, FP64 face records (a separate copy only for FP32) and
+// FP64 areas, partials and the reduction slots.
+struct CurvLayout {
+    size_t off_U[2], off_fi, off_fj, off_ia, off_fi64, off_fj64, off_area, off_parts, off_red, bytes;
+    int nparts;
+};
+
+CurvLayout make_curv_layout(int ni, int nj, int precision) {
+    CurvLayout l{};
+    const int64_t cells = (int64_t)ni * nj;
+    const int64_t nfi = (int64_t)(ni + 1) * nj, nfj = (int64_t)ni * (nj + 1);
+    const size_t es = elem_size(precision);
+    const size_t copy_bytes = (size_t)4 * field_stride(cells) * es;
+    size_t off = 0;
+    l.off_U[0] = off;
+    off += copy_bytes;
+    l.off_U[1] = off;
+    off += copy_bytes;
+    l.off_fi = off;
+    off += align256((size_t)kCurvFaceFields * nfi * es);
+    l.off_fj = off;
+    off += align256((size_t)kCurvFaceFields * nfj * es);
+    l.off_ia = off;
+    off += align256((size_t)cells * es);
+    if (es == 4) {
+        l.off_fi64 = off;
+        off += align256((size_t)kCurvFaceFields * nfi * sizeof(double));
+        l.off_fj64 = off;
+        off += align256((size_t)kCurvFaceFields * nfj * sizeof(double));
+    } else {
+        l.off_fi64 = l.off_fi;
+        l.off_fj64 = l.off_fj;
+    }
+    l.off_area = off;
+    off += align256((size_t)cells * sizeof(double));
+    rtlbfs_mesh m{};
+    m.dim = 2;
+    m.n[0] = ni;
+    m.n[1] = nj;
+    m.n[2] = 1;
+    l.nparts = std::max(kRedBlocks, curv_blocks(m));
+    l.off_parts = off;
+    off += align256(sizeof(double) * (size_t)l.nparts * 8);
+    l.off_red = off;
+    off += align256(sizeof(double) * 32);
+    l.bytes = off;
+    return l;
+}
+
+template <typename R>
+void put(char *dst, const std::vector<double> &src) {
+    R *p = (R *)dst;
+    for (size_t k = 0; k < src.size(); ++k) p[k] = (R)src[k];
 }
 
 }  // namespace
@@ -614,6 +729,7 @@ int rtlbfs_residual(rtlbfs_t h, double *res_u, double *res_T) {
 
 int rtlbfs_nusselt(rtlbfs_t h, rtlbfs_nu *out) {
     if (!h || !out) return RTLBFS_EINVAL;
+    if (h->curv) return fail(h, RTLBFS_EUNSUPPORTED, "body-fitted mesh: use rtlbfs_wall_heat");
     const int ha = heat_axis(h->mesh, h->bc);
     if (ha < 0) return fail(h, RTLBFS_EINVAL, "no pair of isothermal walls");
     const double Tlo = h->bc.Tdev[2 * ha], Thi = h->bc.Tdev[2 * ha + 1];
@@ -720,7 +836,12 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
     for (int a = 0; a < 3; ++a) out->length[a] = a < h->mesh.dim ? h->length[a] : 1.0;
     out->precision = h->opts.precision;
     for (int t = 0; t < kNumTiles2; ++t) out->tune_ms[t] = h->tune_ms[t];
-    if (h->mesh.dim == 2) {
+    if (h->curv) {
+        out->tile_x = kCTX;
+        out->tile_y = kCTY;
+        out->tile_z = 1;
+        out->steps_per_launch = 1;
+    } else if (h->mesh.dim == 2) {
         out->tile_x = kTiles2[h->tile].tx;
         out->tile_y = kTiles2[h->tile].ty;
         out->steps_per_launch = kTiles2[h->tile].nsub;
@@ -731,6 +852,236 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
         out->tile_z = kTZ3;
         out->steps_per_launch = 1;
     }
+    return RTLBFS_OK;
+}
+
+size_t rtlbfs_curv_workspace_bytes(const rtlbfs_curv_mesh *mesh, const rtlbfs_opts *opts) {
+    if (!mesh || mesh->n[0] < 4 || mesh->n[1] < 4 || mesh->n[0] > (1 << 20) || mesh->n[1] > (1 << 20)) return 0;
+    rtlbfs_opts o;
+    if (opts) o = *opts;
+    else rtlbfs_opts_init(&o);
+    return make_curv_layout(mesh->n[0], mesh->n[1], o.precision).bytes;
+}
+
+int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, double beta_g, const rtlbfs_curv_bc *bc,
+                       const rtlbfs_opts *opts, void *hip_stream, void *workspace, size_t ws_bytes, rtlbfs_t *out) {
+    if (!out) return RTLBFS_EINVAL;
+    *out = nullptr;
+    g_create_err.clear();
+    rtlbfs_opts o;
+    if (opts) o = *opts;
+    else rtlbfs_opts_init(&o);
+    auto reject = [](const char *why) {
+        g_create_err = why;
+        return RTLBFS_EINVAL;
+    };
+    if (o.precision != RTLBFS_FP64_PLAIN && o.precision != RTLBFS_FP32_DEV && o.precision != RTLBFS_FP64_DEV)
+        return reject("unknown precision");
+    if (o.method != RTLBFS_METHOD_RTLBFS && o.method != RTLBFS_METHOD_TLBFS) return reject("unknown opts.method");
+    if (o.tile != 0) return reject("opts.tile must be 0 on a body-fitted mesh");
+    if (!(nu > 0.0) || !(chi > 0.0) || !(beta_g >= 0.0)) return reject("nu, chi > 0, beta_g >= 0");
+    if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return reject("dtl and dt must be >= 0");
+    CurvProblem cp;
+    std::string why;
+    int rc = curv_setup(mesh, bc, cp, why);
+    if (rc != RTLBFS_OK) {
+        g_create_err = why;
+        return rc;
+    }
+    Problem P;
+    P.mesh.dim = 2;
+    P.mesh.n[0] = cp.ni;
+    P.mesh.n[1] = cp.nj;
+    P.mesh.n[2] = 1;
+    for (int s = 0; s < 6; ++s) {
+        P.bc.kind[s] = s < 4 ? bc->kind[s] : RTLBFS_PERIODIC;
+        P.bc.Tdev[s] = s < 4 ? bc->Tw[s] - kT0 : 0.0;
+    }
+    P.bc.gravity_axis = -1;  // buoyancy along bc->up, applied by the body-fitted kernel
+    P.D = 2;
+    P.cells = cp.cells;
+    P.nu = nu;
+    P.chi = chi;
+    P.bg = beta_g;
+    P.dtl = o.dtl > 0.0 ? o.dtl : 1.0;
+    P.dt = o.dt > 0.0 ? o.dt : std::min(0.5, 0.15 / std::max(nu, chi));
+
+    rtlbfs_t h = new (std::nothrow) rtlbfs_handle();
+    if (!h) return RTLBFS_ENOMEM;
+    h->curv = true;
+    h->mesh = P.mesh;
+    h->bc = P.bc;
+    if (o.residual_every <= 0) o.residual_every = 100;
+    if (o.mass_fix_every == 0) o.mass_fix_every = 1000;
+    h->opts = o;
+    h->opts.dtl = P.dtl;
+    h->opts.dt = P.dt;
+    h->opts.nu = nu;
+    h->opts.chi = chi;
+    h->opts.beta_g = beta_g;
+    h->opts.phys_given = 1;
+    h->stream = (hipStream_t)hip_stream;
+    const CurvLayout cl = make_curv_layout(cp.ni, cp.nj, o.precision);
+    h->lay = Layout{};
+    h->lay.off_U[0] = cl.off_U[0];
+    h->lay.off_U[1] = cl.off_U[1];
+    h->lay.off_parts = cl.off_parts;
+    h->lay.off_red = cl.off_red;
+    h->lay.bytes = cl.bytes;
+    h->lay.cells = cp.cells;
+    h->lay.nparts = cl.nparts;
+    h->L = 0.0;
+    for (int s = 0; s < 4; ++s) {
+        h->ckind[s] = bc->kind[s];
+        h->cTw[s] = bc->Tw[s];
+    }
+    h->nfi = cp.nfi;
+    h->nfj = cp.nfj;
+    h->ccx = cp.cx;
+    h->ccy = cp.cy;
+    h->carea = cp.area;
+    Domain &d = h->dom;
+    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, d);
+    const bool dev = o.precision != RTLBFS_FP64_PLAIN;
+    d.phd.Tref_s = dev ? bc->T_ref - kT0 : bc->T_ref;
+    d.phf.Tref_s = (float)d.phd.Tref_s;
+
+    if (workspace) {
+        if (ws_bytes < cl.bytes) {
+            delete h;
+            g_create_err = "workspace smaller than rtlbfs_curv_workspace_bytes()";
+            return RTLBFS_ENOMEM;
+        }
+        h->ws = (char *)workspace;
+    } else {
+        hipError_t e = hipMalloc((void **)&h->ws, cl.bytes);
+        if (e != hipSuccess) {
+            delete h;
+            g_create_err = "hipMalloc of the workspace failed";
+            return RTLBFS_ENOMEM;
+        }
+        h->own_ws = true;
+    }
+    {
+        std::vector<double> ia(cp.cells);
+        for (int64_t c = 0; c < cp.cells; ++c) ia[c] = 1.0 / cp.area[c];
+        std::vector<char> bfi, bfj, bia;
+        const size_t es = elem_size(o.precision);
+        bfi.resize(cp.fi.size() * es);
+        bfj.resize(cp.fj.size() * es);
+        bia.resize(ia.size() * es);
+        if (es == 4) {
+            put<float>(bfi.data(), cp.fi);
+            put<float>(bfj.data(), cp.fj);
+            put<float>(bia.data(), ia);
+        } else {
+            put<double>(bfi.data(), cp.fi);
+            put<double>(bfj.data(), cp.fj);
+            put<double>(bia.data(), ia);
+        }
+        hipError_t e = hipMemcpy(h->ws + cl.off_fi, bfi.data(), bfi.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(h->ws + cl.off_fj, bfj.data(), bfj.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(h->ws + cl.off_ia, bia.data(), bia.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && es == 4)
+            e = hipMemcpy(h->ws + cl.off_fi64, cp.fi.data(), cp.fi.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess && es == 4)
+            e = hipMemcpy(h->ws + cl.off_fj64, cp.fj.data(), cp.fj.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(h->ws + cl.off_area, cp.area.data(), cp.area.size() * sizeof(double), hipMemcpyHostToDevice);
+        const uint32_t zero2[2] = {0u, 0u};
+        if (e == hipSuccess) e = hipMemcpy(h->ctr(), zero2, sizeof(zero2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_buf, 64 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            int r2 = hip_fail(h, e, "upload geometry / capture stream");
+            g_create_err = h->err;
+            rtlbfs_destroy(h);
+            return r2;
+        }
+    }
+    d.vol = (const double *)(h->ws + cl.off_area);
+    for (int a = 0; a < 3; ++a) {
+        d.w[a] = nullptr;
+        d.geo[a] = nullptr;
+    }
+    h->fi64 = (const double *)(h->ws + cl.off_fi64);
+    h->fj64 = (const double *)(h->ws + cl.off_fj64);
+    CurvGeo &g = h->cg;
+    g.fi = h->ws + cl.off_fi;
+    g.fj = h->ws + cl.off_fj;
+    g.inv_area = h->ws + cl.off_ia;
+    g.sfi = cp.nfi;
+    g.sfj = cp.nfj;
+    for (int a = 0; a < 2; ++a) {
+        g.up[a] = bc->up[a];
+        g.uinf[a] = bc->u_inf[a];
+        g.upf[a] = (float)bc->up[a];
+        g.uinff[a] = (float)bc->u_inf[a];
+    }
+    g.Tinf_s = dev ? bc->T_inf - kT0 : bc->T_inf;
+    g.Tinff_s = (float)g.Tinf_s;
+
+    // initial state: the far-field state, seeded noise on T
+    const int64_t N = cp.cells;
+    std::vector<double> rho((size_t)N, 1.0), u((size_t)N * 2), T((size_t)N);
+    for (int64_t c = 0; c < N; ++c) {
+        u[c] = bc->u_inf[0];
+        u[N + c] = bc->u_inf[1];
+        T[c] = bc->T_inf - kT0 + o.noise_amp * splitmix_uniform(o.seed, (uint64_t)c);
+    }
+    rc = upload_prims(h, rho.data(), u.data(), T.data());
+    if (rc == RTLBFS_OK) {
+        hipError_t e = enqueue_integrals(h, h->int_out(), h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->m0(), h->int_out(), sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = hip_fail(h, e, "initial integrals");
+    }
+    if (rc != RTLBFS_OK) {
+        g_create_err = h->err;
+        rtlbfs_destroy(h);
+        return rc;
+    }
+    h->tile = 0;
+    *out = h;
+    return RTLBFS_OK;
+}
+
+int rtlbfs_wall_heat(rtlbfs_t h, int side, double out[2]) {
+    if (!h || !out) return RTLBFS_EINVAL;
+    if (!h->curv) return fail(h, RTLBFS_EUNSUPPORTED, "rtlbfs_wall_heat needs a body-fitted mesh");
+    if (side < 0 || side > 3 || h->ckind[side] != RTLBFS_WALL_ISOTHERMAL)
+        return fail(h, RTLBFS_EINVAL, "side is not an isothermal wall");
+    double *dst = h->red() + 5;
+    switch (h->opts.precision) {
+        case RTLBFS_FP64_PLAIN:
+            k_curv_wall_heat<double, false><<<1, 256, 0, h->stream>>>(h->dom, h->fi64, h->fj64, h->nfi, h->nfj,
+                                                                      (const double *)h->U(h->cur), side, h->cTw[side], dst);
+            break;
+        case RTLBFS_FP64_DEV:
+            k_curv_wall_heat<double, true><<<1, 256, 0, h->stream>>>(h->dom, h->fi64, h->fj64, h->nfi, h->nfj,
+                                                                     (const double *)h->U(h->cur), side, h->cTw[side], dst);
+            break;
+        default:
+            k_curv_wall_heat<float, true><<<1, 256, 0, h->stream>>>(h->dom, h->fi64, h->fj64, h->nfi, h->nfj,
+                                                                    (const float *)h->U(h->cur), side, h->cTw[side], dst);
+            break;
+    }
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipMemcpyAsync(h->host_buf + 40, dst, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out[0] = h->host_buf[40];
+    out[1] = h->host_buf[41];
+    return RTLBFS_OK;
+}
+
+int rtlbfs_curv_cells(rtlbfs_t h, double *cx, double *cy, double *area, size_t count) {
+    if (!h) return RTLBFS_EINVAL;
+    if (!h->curv) return fail(h, RTLBFS_EUNSUPPORTED, "not a body-fitted mesh");
+    if (count < h->ccx.size()) return fail(h, RTLBFS_EINVAL, "count smaller than the cell count");
+    if (cx) std::memcpy(cx, h->ccx.data(), h->ccx.size() * sizeof(double));
+    if (cy) std::memcpy(cy, h->ccy.data(), h->ccy.size() * sizeof(double));
+    if (area) std::memcpy(area, h->carea.data(), h->carea.size() * sizeof(double));
     return RTLBFS_OK;
 }
 

@@ -25,10 +25,15 @@ enum : int { kGeoW = 0, kGeoInvW, kGeoLoSelf, kGeoLoNb, kGeoHiSelf, kGeoHiNb, kG
 // Physical and lattice constants of the step: viscosity, diffusivity, lattice
 // step, relaxation times (Eqs. 9-10), buoyancy beta*g, the time step Delta-t,
 // and the lattice spacing h = c dt with its finite-difference factors.
+// Tref_s: reference temperature of the buoyancy in the storage convention
+// (absolute T, or T - T0 with deviation storage), read only by kernels that
+// take it from here (face fluxes instantiated with TB); the Cartesian kernels
+// use T_ref = T0.
 template <typename R>
 struct Phys {
     R nu, chi, dtl, tau_f, tau_g, bg, dt;
     R h, inv2h, invh2, inv4h2;
+    R Tref_s;
 };
 
 // One structured domain as the kernels see it.  Lengths in lattice units;
@@ -52,6 +57,7 @@ struct Domain {
     Phys<float> phf;     // the constants above, in FP32 and in FP64
     Phys<double> phd;
     float Twf[6];        // Tw in FP32
+    const double *vol;   // body-fitted meshes: cell areas (device, FP64); null on Cartesian meshes
 };
 
 // ------------------------------------------------------------ reductions --
@@ -140,7 +146,7 @@ struct Side {
 // its products to the central-difference accumulators of Eqs. 46-48:
 // D_k f = (f(+k) - f(-k))/2h, D_kk f = (f(+k) - 2 f(0) + f(-k))/h^2,
 // D_kl f = (f(+k+l) - f(+k-l) - f(-k+l) + f(-k-l))/4h^2.
-template <typename R, int D, bool DEV>
+template <typename R, int D, bool DEV, bool TB = false>
 __host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR, const R (&fdir)[D],
                                  const Phys<R> &ph, R (&out)[D + 2]) {
     constexpr int NP = D + 2;
@@ -239,7 +245,7 @@ __host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> 
     const R dt = ph.dtl, dt2h = half * ph.dtl * ph.dtl;
     const R rho0 = DEV ? (R)1 + r0 : r0;
     // Buoyancy at the face centre (Eq. 64).
-    const R Fb = ph.bg * rho0 * (DEV ? T0n : T0n - (R)kT0);
+    const R Fb = ph.bg * rho0 * (TB ? T0n - ph.Tref_s : (DEV ? T0n : T0n - (R)kT0));
     // Eqs. 46-48 as increments over the face-centre values.
     const R dr = -dt * divm + dt2h * (ddK + cs2 * lapr);
     R dm[D], ms[D];
@@ -282,7 +288,7 @@ __host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> 
 // sum w e = 0 and sum w e e = c_s^2 I; the energy is carried as theta with
 // rho T = T0 rho + theta and the theta flux Q - T0 P assembled from small
 // terms (A = e.u / c_s^2 + (e.u)^2 / 2c_s^4 - u^2 / 2c_s^2, B = e.u / c_s^2).
-template <typename R, int D, bool DEV>
+template <typename R, int D, bool DEV, bool TB = false>
 __host__ __device__ inline void face_flux_tlbfs(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR,
                                        const R (&fdir)[D], const Phys<R> &ph, R (&out)[D + 2]) {
     constexpr int NP = D + 2;
@@ -381,7 +387,7 @@ __host__ __device__ inline void face_flux_tlbfs(const Side<R, D> &L, const Side<
                 }
             }
     // buoyancy in the predicted momentum, at the face centre (Eq. 64)
-    const R Fb = ph.bg * rho_c * (DEV ? T_c : T_c - (R)kT0);
+    const R Fb = ph.bg * rho_c * (TB ? T_c - ph.Tref_s : (DEV ? T_c : T_c - (R)kT0));
     const R dt = ph.dtl;
 #pragma unroll
     for (int k = 0; k < D; ++k) ms[k] += dt * fdir[k] * Fb;

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librtlbfs.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5, -6
-PERIODIC, WALL_ISOTHERMAL, WALL_ADIABATIC = 0, 1, 2
+PERIODIC, WALL_ISOTHERMAL, WALL_ADIABATIC, FARFIELD = 0, 1, 2, 3
 FP64_PLAIN, FP32_DEV, FP64_DEV = 0, 1, 2
 INIT_REST, INIT_CONDUCTION = 0, 1
 METHOD_RTLBFS, METHOD_TLBFS = 0, 1
@@ -50,6 +50,15 @@ class Opts(C.Structure):
         ("round_nearest", C.c_int),
         ("method", C.c_int),
     ]
+
+
+class CurvMesh(C.Structure):
+    _fields_ = [("n", C.c_int * 2), ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double))]
+
+
+class CurvBC(C.Structure):
+    _fields_ = [("kind", C.c_int * 4), ("Tw", C.c_double * 4), ("up", C.c_double * 2), ("T_ref", C.c_double),
+                ("u_inf", C.c_double * 2), ("T_inf", C.c_double)]
 
 
 class NuOut(C.Structure):
@@ -121,6 +130,12 @@ def load_library() -> C.CDLL:
     lib.rtlbfs_set_state.argtypes = [VP, PD, PD, PD, SZ]
     lib.rtlbfs_get_info.argtypes = [VP, C.POINTER(Info)]
     lib.rtlbfs_destroy.argtypes = [VP]
+    lib.rtlbfs_curv_workspace_bytes.argtypes = [C.POINTER(CurvMesh), C.POINTER(Opts)]
+    lib.rtlbfs_curv_workspace_bytes.restype = SZ
+    lib.rtlbfs_curv_create.argtypes = [C.POINTER(CurvMesh), D, D, D, C.POINTER(CurvBC), C.POINTER(Opts), VP, VP, SZ,
+                                       C.POINTER(VP)]
+    lib.rtlbfs_wall_heat.argtypes = [VP, I, PD]
+    lib.rtlbfs_curv_cells.argtypes = [VP, PD, PD, PD, SZ]
     lib.rtlbfs_batch_workspace_bytes.argtypes = [I, C.POINTER(Mesh), C.POINTER(Opts)]
     lib.rtlbfs_batch_workspace_bytes.restype = SZ
     lib.rtlbfs_batch_create.argtypes = [I, C.POINTER(Mesh), PD, PD, D, C.POINTER(BC), C.POINTER(Opts), VP, VP, SZ,
@@ -135,7 +150,8 @@ def load_library() -> C.CDLL:
     lib.rtlbfs_batch_destroy.argtypes = [VP]
     for name in ("rtlbfs_opts_init", "rtlbfs_mesh_nodes", "rtlbfs_create", "rtlbfs_step", "rtlbfs_sync",
                  "rtlbfs_residual", "rtlbfs_nusselt", "rtlbfs_integrals", "rtlbfs_get_field", "rtlbfs_get_stored",
-                 "rtlbfs_set_state", "rtlbfs_get_info", "rtlbfs_destroy", "rtlbfs_batch_create", "rtlbfs_batch_step",
+                 "rtlbfs_set_state", "rtlbfs_get_info", "rtlbfs_destroy", "rtlbfs_curv_create", "rtlbfs_wall_heat",
+                 "rtlbfs_curv_cells", "rtlbfs_batch_create", "rtlbfs_batch_step",
                  "rtlbfs_batch_nusselt", "rtlbfs_batch_residual", "rtlbfs_batch_get_field", "rtlbfs_batch_get_info",
                  "rtlbfs_batch_sync", "rtlbfs_batch_diverged", "rtlbfs_batch_destroy"):
         getattr(lib, name).restype = I
@@ -299,6 +315,65 @@ class Solver:
 
     def grid(self, values: np.ndarray) -> np.ndarray:
         return values.reshape(tuple(reversed(self.shape)))
+
+
+class CurvSolver(Solver):
+    """One 2D body-fitted (structured curvilinear) mesh advanced by the gfx950
+    kernels: vertex arrays x, y of shape (nj + 1, ni + 1), sides (i-, i+, j-,
+    j+) of kinds PERIODIC / WALL_ISOTHERMAL / WALL_ADIABATIC / FARFIELD,
+    absolute temperatures, buoyancy beta_g (T - T_ref) along the unit vector
+    `up`, far-field state (u_inf, T_inf, rho = 1) that is also the initial
+    state."""
+
+    def __init__(self, x: np.ndarray, y: np.ndarray, kind: Sequence[int], Tw: Sequence[float] = (0.0,) * 4,
+                 up: Sequence[float] = (0.0, 0.0), T_ref: float = 0.0, u_inf: Sequence[float] = (0.0, 0.0),
+                 T_inf: float = 0.0, nu: float = 0.1, chi: float = 0.1, beta_g: float = 0.0, **opts):
+        self._h = None
+        self._lib = load_library()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        if x.ndim != 2 or x.shape != y.shape:
+            raise ValueError("x and y must be (nj + 1, ni + 1) arrays")
+        self.dim = 2
+        self.cmesh = CurvMesh()
+        self.cmesh.n[:] = [x.shape[1] - 1, x.shape[0] - 1]
+        self.cmesh.x, self.cmesh.y = _pd(x), _pd(y)
+        self._xy = (x, y)  # keep the vertex arrays alive for the create call
+        self.cbc = CurvBC()
+        self.cbc.kind[:] = [int(v) for v in kind]
+        self.cbc.Tw[:] = [float(v) for v in Tw]
+        self.cbc.up[:] = [float(v) for v in up]
+        self.cbc.T_ref = float(T_ref)
+        self.cbc.u_inf[:] = [float(v) for v in u_inf]
+        self.cbc.T_inf = float(T_inf)
+        self.opts = make_opts(**opts)
+        nbytes = self._lib.rtlbfs_curv_workspace_bytes(C.byref(self.cmesh), C.byref(self.opts))
+        if nbytes == 0:
+            raise RtlbfsError(EINVAL, "invalid mesh")
+        self.workspace, self.stream = _torch_stream_and_alloc(nbytes)
+        h = C.c_void_p()
+        rc = self._lib.rtlbfs_curv_create(C.byref(self.cmesh), nu, chi, beta_g, C.byref(self.cbc),
+                                          C.byref(self.opts), C.c_void_p(self.stream),
+                                          C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), C.byref(h))
+        if rc != OK:
+            detail = self._lib.rtlbfs_last_error(None).decode()
+            raise RtlbfsError(rc, f"rtlbfs_curv_create: {strerror(rc)}: {detail}")
+        self._h = h
+        self.info = self.get_info()
+        self.cells = int(self.info.cells)
+        self.shape = (int(self.cmesh.n[0]), int(self.cmesh.n[1]))
+
+    def wall_heat(self, side: int) -> tuple[float, float]:
+        """(sum (T_w - T_P)/d dS, sum dS) over the faces of an isothermal side."""
+        out = np.zeros(2)
+        self._check(self._lib.rtlbfs_wall_heat(self._h, side, _pd(out)), "rtlbfs_wall_heat")
+        return float(out[0]), float(out[1])
+
+    def geometry(self) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """Cell centroids (x, y) and areas the library derived."""
+        cx, cy, a = np.zeros(self.cells), np.zeros(self.cells), np.zeros(self.cells)
+        self._check(self._lib.rtlbfs_curv_cells(self._h, _pd(cx), _pd(cy), _pd(a), self.cells), "rtlbfs_curv_cells")
+        return cx, cy, a
 
 
 class Batch:

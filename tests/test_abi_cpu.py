@@ -145,3 +145,89 @@ def test_product_package_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "rtlbfs_oracle" not in text and "orc_" not in text, f
+
+
+# ------------------------------------------------------ body-fitted meshes --
+
+def _curv_mesh(ni=12, nj=8, periodic=True):
+    import inputs
+    x, y = inputs.o_mesh(ni, nj, 10.0, 30.0, 1.5)
+    return x, y
+
+
+def _curv_create(x, y, bc, nu=0.1, chi=0.1, beta_g=0.0, opts=None):
+    lib = rt.load_library()
+    m = rtb.CurvMesh()
+    m.n[:] = [x.shape[1] - 1, x.shape[0] - 1]
+    x = np.ascontiguousarray(x)
+    y = np.ascontiguousarray(y)
+    m.x, m.y = rtb._pd(x), rtb._pd(y)
+    o = opts or rt.make_opts()
+    h = C.c_void_p()
+    rc = lib.rtlbfs_curv_create(C.byref(m), nu, chi, beta_g, C.byref(bc), C.byref(o), None, None, 0, C.byref(h))
+    return rc, h
+
+
+def _curv_bc(kind=(0, 0, 1, 3), up=(0.0, 1.0)):
+    b = rtb.CurvBC()
+    b.kind[:] = list(kind)
+    b.Tw[:] = [0.0, 0.0, 1.0, 0.0]
+    b.up[:] = list(up)
+    b.u_inf[:] = [0.05, 0.0]
+    return b
+
+
+@pytest.mark.parametrize("case", ["small", "kind", "pair", "not_closed", "folded", "up", "tile", "nu", "beta_g",
+                                  "precision", "method", "nan"])
+def test_curv_create_rejects_invalid_problems_before_touching_the_device(case):
+    x, y = _curv_mesh()
+    bc = _curv_bc()
+    kw = {}
+    if case == "small":
+        x, y = x[:, :4], y[:, :4]
+        bc.kind[0] = bc.kind[1] = rt.WALL_ADIABATIC
+    elif case == "kind":
+        bc.kind[3] = 4
+    elif case == "pair":
+        bc.kind[1] = rt.WALL_ADIABATIC
+    elif case == "not_closed":
+        x = x.copy()
+        x[:, -1] += 0.5  # the last vertex column no longer meets the first
+    elif case == "folded":
+        x, y = x.copy(), y.copy()
+        x[3, 4], x[4, 4] = x[4, 4], x[3, 4]  # two radial vertices swapped
+        y[3, 4], y[4, 4] = y[4, 4], y[3, 4]
+    elif case == "up":
+        bc.up[:] = [0.5, 0.5]
+    elif case == "tile":
+        kw["opts"] = rt.make_opts(tile=1)
+    elif case == "nu":
+        kw["nu"] = 0.0
+    elif case == "beta_g":
+        kw["beta_g"] = -1.0
+    elif case == "precision":
+        kw["opts"] = rt.make_opts(precision=5)
+    elif case == "method":
+        kw["opts"] = rt.make_opts(method=3)
+    elif case == "nan":
+        x = x.copy()
+        x[2, 2] = np.nan
+    rc, h = _curv_create(x, y, bc, **kw)
+    assert rc == rt.EINVAL and not h.value, rt.load_library().rtlbfs_last_error(None)
+
+
+def test_curv_workspace_bytes_and_cartesian_only_calls():
+    lib = rt.load_library()
+    m = rtb.CurvMesh()
+    m.n[:] = [450, 300]
+    o64, o32 = rt.make_opts(), rt.make_opts(precision=rt.FP32_DEV)
+    b64 = lib.rtlbfs_curv_workspace_bytes(C.byref(m), C.byref(o64))
+    b32 = lib.rtlbfs_curv_workspace_bytes(C.byref(m), C.byref(o32))
+    cells = 450 * 300
+    assert b64 >= 2 * 4 * cells * 8 + 8 * 2 * cells * 8 and b64 % 256 == 0
+    assert b32 >= 2 * 4 * cells * 4 + 8 * 2 * cells * (4 + 8)  # FP32 records plus the FP64 copy
+    m.n[:] = [3, 300]
+    assert lib.rtlbfs_curv_workspace_bytes(C.byref(m), C.byref(o64)) == 0
+    out = np.zeros(2)
+    assert lib.rtlbfs_wall_heat(None, 2, rtb._pd(out)) == rt.EINVAL
+    assert lib.rtlbfs_curv_cells(None, None, None, None, 0) == rt.EINVAL

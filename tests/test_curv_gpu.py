@@ -1,0 +1,151 @@
+"""Body-fitted 2D meshes on the GPU against the curvilinear oracle (the
+setting of Secs. 4.3 and 4.5: O-type meshes, per-face normals, the face
+lattice aligned with each face, far-field and curved-wall boundaries).
+
+The library derives its geometry (centroids, areas, face records) on its own
+from the vertex arrays; the oracle derives its own.  Meshes are ragged over
+the kernel's 16 x 16 tiles.
+"""
+import numpy as np
+import pytest
+
+import inputs
+import paper_2202_13449_amd as rt
+from oracle import RTLBFS, TLBFS, CurvConfig, CurvOracle
+
+pytestmark = pytest.mark.gpu
+
+ISO, ADI, PER, FAR = rt.WALL_ISOTHERMAL, rt.WALL_ADIABATIC, rt.PERIODIC, rt.FARFIELD
+FP64_TOL = 1e-12
+
+
+def wavy_box():
+    xn = np.linspace(0.0, 37.0, 38)
+    yn = np.linspace(0.0, 23.0, 22)
+    return inputs.wavy_vertices(xn, yn, 0.05)  # 37 x 21 cells
+
+
+def annulus(ni=40, nj=21, r_in=30.0, r_out=200.0, first=1.0):
+    return inputs.o_mesh(ni, nj, r_in, r_out, first, theta0=-0.5 * np.pi)
+
+
+def make_pair(x, y, precision=rt.FP64_PLAIN, method=rt.METHOD_RTLBFS, dt=0.5, **bc):
+    """GPU solver and oracle of the same body-fitted problem."""
+    kind = bc.pop("kind")
+    phys = dict(nu=bc.pop("nu", 0.08), chi=bc.pop("chi", 0.11), beta_g=bc.pop("beta_g", 2e-4))
+    s = rt.CurvSolver(x, y, kind, precision=precision, method=method, dt=dt, residual_every=25, **phys, **bc)
+    cfg = CurvConfig(bc=tuple(kind), Tw=tuple(bc.get("Tw", (0.0,) * 4)), up=tuple(bc.get("up", (0.0, 0.0))),
+                     Tb=bc.get("T_ref", 0.0), u_inf=tuple(bc.get("u_inf", (0.0, 0.0))), T_inf=bc.get("T_inf", 0.0),
+                     dt=dt, deviation=0 if precision == rt.FP64_PLAIN else 1,
+                     method=RTLBFS if method == rt.METHOD_RTLBFS else TLBFS, **phys)
+    return s, CurvOracle(cfg, x, y)
+
+
+def rel_errors(s, o, Vc):
+    out = []
+    for f in range(4):
+        a, b = s.field(f), o.prim(f)
+        scale = 1.0 if f == 0 else (max(np.abs(b).max(), Vc) if f < 3 else np.abs(b).max())
+        if f == 0:
+            a, b = a - 1.0, b - 1.0
+            scale = max(np.abs(b).max(), 1e-300)
+        out.append(float(np.abs(a - b).max() / scale))
+    return out
+
+
+BOX = dict(kind=(ISO, ISO, ADI, ADI), Tw=(1.0, 0.0, 0.0, 0.0), up=(0.0, 1.0), T_ref=0.5, T_inf=0.5)
+CYL = dict(kind=(PER, PER, ISO, FAR), Tw=(0.0, 0.0, 1.0, 0.0), up=(0.0, 1.0), T_ref=0.0, u_inf=(0.0, 0.04),
+           T_inf=0.0, beta_g=4e-5)
+
+
+def test_geometry_matches_the_oracle():
+    for (x, y), bc in ((wavy_box(), BOX), (annulus(), CYL)):
+        s, o = make_pair(x, y, **bc)
+        a, b = s.geometry(), o.cells()
+        for k in range(3):
+            assert np.abs(a[k] - b[k]).max() <= 1e-12 * np.abs(b[k]).max(), k
+
+
+@pytest.mark.parametrize("precision", [rt.FP64_PLAIN, rt.FP64_DEV])
+@pytest.mark.parametrize("method", [rt.METHOD_RTLBFS, rt.METHOD_TLBFS])
+def test_wavy_box_parity(precision, method):
+    """Closed box with bent cells, isothermal side walls, buoyancy: 120 steps
+    from a random state."""
+    x, y = wavy_box()
+    s, o = make_pair(x, y, precision, method, **BOX)
+    rho, u, T = inputs.random_state(s.cells, 2, seed=61)
+    s.set_state(rho, u, T)
+    o.set_prim(rho, u, T)
+    s.step(120)
+    o.step(120)
+    rel = rel_errors(s, o, 0.02)
+    assert max(rel) <= FP64_TOL, rel
+    ra, rb = s.residual(), o.residual()
+    assert np.allclose(ra, rb, rtol=1e-9), (ra, rb)
+    for side in (0, 1):
+        ha, hb = s.wall_heat(side), o.wall_heat(side)
+        assert abs(ha[0] - hb[0]) <= 1e-11 * abs(hb[0]) and abs(ha[1] - hb[1]) <= 1e-12 * hb[1]
+
+
+@pytest.mark.parametrize("precision", [rt.FP64_PLAIN, rt.FP64_DEV])
+@pytest.mark.parametrize("method", [rt.METHOD_RTLBFS, rt.METHOD_TLBFS])
+def test_heated_cylinder_annulus_parity(precision, method):
+    """O-mesh around a heated cylinder (periodic around, isothermal wall,
+    far field with an upward stream, aiding buoyancy): 200 steps from the
+    free stream, 40 x 21 cells (ragged over the tiles, the periodic seam
+    inside a tile row)."""
+    x, y = annulus()
+    s, o = make_pair(x, y, precision, method, **CYL)
+    s.step(200)
+    o.step(200)
+    rel = rel_errors(s, o, 0.04)
+    assert max(rel) <= FP64_TOL, rel
+    ha, hb = s.wall_heat(2), o.wall_heat(2)
+    assert abs(ha[0] - hb[0]) <= 1e-11 * abs(hb[0])
+
+
+def test_heated_cylinder_fp32_deviation():
+    """FP32 deviation storage with stochastic rounding against the FP64
+    oracle: relative field errors at the FP32 rounding level."""
+    x, y = annulus()
+    s, o = make_pair(x, y, rt.FP32_DEV, **CYL)
+    s.step(200)
+    o.step(200)
+    rel = rel_errors(s, o, 0.04)
+    assert max(rel[1:]) <= 1e-5 and rel[0] <= 1e-4, rel
+    ha, hb = s.wall_heat(2), o.wall_heat(2)
+    assert abs(ha[0] - hb[0]) <= 1e-5 * abs(hb[0])
+
+
+@pytest.mark.parametrize("precision", [rt.FP64_PLAIN, rt.FP32_DEV])
+def test_uniform_far_field_state_is_preserved(precision):
+    """No body: far field on both radial sides, the far-field state stays
+    uniform (the face normals of every cell sum to zero)."""
+    x, y = annulus(ni=33, nj=18, r_in=40.0, r_out=160.0, first=3.0)
+    s = rt.CurvSolver(x, y, (PER, PER, FAR, FAR), up=(0.0, 1.0), T_ref=0.3, u_inf=(0.03, -0.012), T_inf=0.3,
+                      nu=0.05, chi=0.07, beta_g=1e-4, precision=precision, dt=0.5)
+    s.step(300)
+    tol = 1e-14 if precision == rt.FP64_PLAIN else 1e-6
+    assert np.abs(s.field(0) - 1.0).max() <= tol
+    assert np.abs(s.field(1) - 0.03).max() <= tol * 0.1 + 1e-15
+    assert np.abs(s.field(2) + 0.012).max() <= tol * 0.1 + 1e-15
+    assert np.abs(s.field(3) - 0.3).max() <= tol
+
+
+def test_cylinder_full_size_prefix():
+    """The Sec. 4.3 mesh itself (450 around x 300 outward, first cell
+    0.003 D, far field at 52.5 D), Re = 20, Gr = 100, FP64: 40 steps from
+    the free stream, every cell against the oracle."""
+    from paper_2202_13449_amd.workloads import CYLINDER, cylinder_mesh
+
+    x, y, D = cylinder_mesh()
+    x, y = np.array(x), np.array(y)
+    u_inf = CYLINDER["u_inf_cs"] * np.sqrt(1.0 / 3.0)
+    nu = u_inf * D / CYLINDER["Re"]
+    bc = dict(kind=(PER, PER, ISO, FAR), Tw=(0, 0, 1.0, 0), up=(0.0, 1.0), T_ref=0.0, u_inf=(0.0, u_inf), T_inf=0.0,
+              nu=nu, chi=nu / CYLINDER["Pr"], beta_g=100.0 * nu * nu / D ** 3)
+    s, o = make_pair(x, y, rt.FP64_PLAIN, dt=0.15 / bc["chi"], **bc)  # explicit diffusion limit of the 0.003 D cells
+    s.step(40)
+    o.step(40)
+    rel = rel_errors(s, o, u_inf)
+    assert max(rel) <= FP64_TOL, rel
