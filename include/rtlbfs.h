@@ -48,7 +48,7 @@ extern "C" {
 #define RTLBFS_EINVAL (-1)       /* bad argument or inconsistent problem */
 #define RTLBFS_ENOMEM (-2)       /* device allocation failed or workspace too small */
 #define RTLBFS_EDEVICE (-3)      /* a HIP call failed (text in rtlbfs_last_error) */
-#define RTLBFS_EDIVERGED (-4)    /* NaN/Inf or local Mach > 0.5 seen at a residual step */
+#define RTLBFS_EDIVERGED (-4)    /* NaN/Inf or local Mach >= opts.max_mach seen at a residual step */
 #define RTLBFS_EUNSUPPORTED (-5) /* valid request the library does not implement */
 #define RTLBFS_ESTATE (-6)       /* call order (e.g. a residual before any residual step) */
 
@@ -118,6 +118,9 @@ typedef struct {
                              increments below half an ulp near steady state */
     int method;           /* RTLBFS_METHOD_RTLBFS (default) or RTLBFS_METHOD_TLBFS: the interior-face
                              flux; wall faces, gradients, update and diagnostics are shared */
+    double max_mach;      /* divergence guard: a residual step that sees a local Mach number |u|/c_s
+                             at or above this value (or a NaN/Inf) makes the next synchronising call
+                             return RTLBFS_EDIVERGED; 0 -> 0.5, at most 10 */
 } rtlbfs_opts;
 
 typedef struct {
@@ -184,7 +187,7 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
 int rtlbfs_step(rtlbfs_t h, int64_t n);
 
 /* Wait for the handle's stream.  EDIVERGED if a residual step saw NaN/Inf or
- * Mach > 0.5. */
+ * a local Mach number at or above opts.max_mach. */
 int rtlbfs_sync(rtlbfs_t h);
 
 /* Eq. 65 ratios from the most recent residual step (synchronising):
@@ -231,10 +234,8 @@ int rtlbfs_destroy(rtlbfs_t h);
  * with d the normal distance of the centroid from the wall face.
  *
  * A far-field side (RTLBFS_FARFIELD) is an ordinary face against a ghost
- * cell mirrored across it (same normal distance, zero gradient): where the
- * far-field velocity points into the domain the ghost holds u_inf and T_inf
- * with the fluid cell's density, elsewhere rho = 1 with the fluid cell's
- * velocity and temperature.
+ * cell mirrored across it (same normal distance, zero gradient) that holds
+ * the free stream: rho = 1, u_inf, T_inf.
  *
  * Buoyancy: beta_g rho (T - T_ref) along the unit vector `up`, in the cell
  * update and (unless opts.buoyancy_update_only) in the predicted momentum.
@@ -316,8 +317,8 @@ int rtlbfs_batch_get_field(rtlbfs_batch_t h, int member, int field, double *host
 int rtlbfs_batch_get_info(rtlbfs_batch_t h, int member, rtlbfs_info *out);
 int rtlbfs_batch_sync(rtlbfs_batch_t h);
 /* Per-member divergence flags of the last residual step (synchronising):
- * host_flags[m] = 1 when member m held a NaN/Inf or a local Mach number above
- * 0.5 (the guard evaluated with Eq. 65), else 0.  host_flags holds `count`
+ * host_flags[m] = 1 when member m held a NaN/Inf or a local Mach number at or
+ * above opts.max_mach (the guard evaluated with Eq. 65), else 0.  host_flags holds `count`
  * ints owned by the caller.  A diverged member does not disturb the others,
  * so a parameter sweep keeps stepping the batch and reads the flags (the
  * stability maps of Sec. 3.3, Figs. 4-5).  Returns RTLBFS_ESTATE before the

@@ -23,10 +23,8 @@
  *     (zero mass flux, pressure c_s^2 r, viscous stress with V_n = -3 m_n/d,
  *     V_t = -m_t/d, conduction -chi (rho T_w - e)/d on isothermal walls);
  *   - far field: a ghost cell mirrored across the face (same normal
- *     distance, zero gradient) whose state is the far-field velocity and
- *     temperature with the cell's density where the far-field flow enters,
- *     and the far-field density with the cell's velocity and temperature
- *     where it leaves (sign of u_inf . n); the face is then an ordinary
+ *     distance, zero gradient) that holds the free-stream state Sec. 4.3
+ *     prescribes (rho_inf = 1, u_inf, T_inf); the face is then an ordinary
  *     interior face;
  *   - buoyancy F = beta_g rho (T - T_b) along the given upward unit vector,
  *     with T_b the far-field temperature in mixed convection.
@@ -135,22 +133,14 @@ static void face_at(const orc_curv *s, int axis, int along, int across, face_t *
 
 static double store_T(const orc_curv *s, double Tabs) { return s->c.deviation ? Tabs - T0 : Tabs; }
 
-/* Ghost primitives (storage convention) of a far-field face of cell P with
- * outward normal no. */
-static void ghost_prim(const orc_curv *s, long P, const double *no, double *G)
+/* Ghost primitives (storage convention) of a far-field face: the free
+ * stream. */
+static void ghost_prim(const orc_curv *s, double *G)
 {
-    int inflow = s->c.u_inf[0] * no[0] + s->c.u_inf[1] * no[1] < 0.0;
-    if (inflow) {
-        G[0] = s->prim[0][P];
-        G[1] = s->c.u_inf[0];
-        G[2] = s->c.u_inf[1];
-        G[3] = store_T(s, s->c.T_inf);
-    } else {
-        G[0] = s->c.deviation ? 0.0 : 1.0;
-        G[1] = s->prim[1][P];
-        G[2] = s->prim[2][P];
-        G[3] = s->prim[3][P];
-    }
+    G[0] = s->c.deviation ? 0.0 : 1.0;
+    G[1] = s->c.u_inf[0];
+    G[2] = s->c.u_inf[1];
+    G[3] = store_T(s, s->c.T_inf);
 }
 
 static void compute_primitives(orc_curv *s)
@@ -200,7 +190,7 @@ static void compute_gradients(orc_curv *s)
                     phi[3] = kind == ORC_WALL_ISOTHERMAL ? store_T(s, s->c.Tw[f.side]) : s->prim[3][P];
                 } else { /* far field: mirrored ghost, equal distances */
                     double G[4];
-                    ghost_prim(s, P, no, G);
+                    ghost_prim(s, G);
                     for (int p = 0; p < 4; ++p) phi[p] = 0.5 * (s->prim[p][P] + G[p]);
                 }
                 for (int p = 0; p < 4; ++p)
@@ -288,7 +278,7 @@ static void accumulate_fluxes(orc_curv *s)
                 } else { /* far field: P on the left of the frame (no, to), the ghost on the right */
                     double pL[4], gL[12], pR[4], gR[12], G[4];
                     to_frame(s, P, no, to, pL, gL);
-                    ghost_prim(s, P, no, G);
+                    ghost_prim(s, G);
                     pR[0] = G[0];
                     pR[1] = G[1] * no[0] + G[2] * no[1];
                     pR[2] = G[1] * to[0] + G[2] * to[1];

@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-enum { ORC_FARFIELD = 3 };
+enum { ORC_FARFIELD = 3 }; /* face against a mirrored ghost cell holding the free stream */
 
 typedef struct {
     int ni, nj;             /* cells along i and j */

@@ -69,23 +69,60 @@ __device__ inline R cg_Tinf(const CurvGeo &g) {
     else return g.Tinf_s;
 }
 
+// One side of a face in the face frame (n, t), t = (-n_y, n_x): primitives
+// P = (r, u_x, u_y, T) and their gradients G[p][axis] of a cell, rotated, and
+// shifted by the tangential gradient times tau = (x_S - x_C).t (the Eq. 29
+// values of a centre that lies off the face normal).
+template <typename R>
+__host__ __device__ inline void side_in_frame(const R (&P)[4], const R (&G)[4][2], R nx, R ny, R tau,
+                                              Side<R, 2> &S) {
+    const R tx = -ny, ty = nx;
+    const R e[2][2] = {{nx, ny}, {tx, ty}};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        S.g[k][0] = G[0][0] * e[k][0] + G[0][1] * e[k][1];
+        S.g[k][3] = G[3][0] * e[k][0] + G[3][1] * e[k][1];
+        const R gux = G[1][0] * e[k][0] + G[1][1] * e[k][1];  // d_k u_x, d_k u_y
+        const R guy = G[2][0] * e[k][0] + G[2][1] * e[k][1];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) S.g[k][1 + q] = e[q][0] * gux + e[q][1] * guy;  // d_k u_q = e_q . (grad u) e_k
+    }
+    S.v[0] = P[0] + S.g[1][0] * tau;
+    S.v[1] = P[1] * nx + P[2] * ny + S.g[1][1] * tau;
+    S.v[2] = P[1] * tx + P[2] * ty + S.g[1][2] * tau;
+    S.v[3] = P[3] + S.g[1][3] * tau;
+}
+
+// Interior-face flux (RTLBFS, or TLBFS when TL) along +n times the face area,
+// momentum back in global components; the buoyancy direction `up` enters
+// the predictor in the face frame when fp.
+template <typename R, bool DEV, bool TL>
+__host__ __device__ inline void frame_flux(const Side<R, 2> &A, const Side<R, 2> &B, R dL, R dR, R nx, R ny, R upx,
+                                           R upy, bool fp, R dS, const Phys<R> &ph, R (&Fg)[4]) {
+    const R tx = -ny, ty = nx;
+    const R fdir[2] = {fp ? upx * nx + upy * ny : (R)0, fp ? upx * tx + upy * ty : (R)0};
+    R G[4];
+    if constexpr (TL) face_flux_tlbfs<R, 2, DEV, true>(A, B, dL, dR, fdir, ph, G);
+    else face_flux<R, 2, DEV, true>(A, B, dL, dR, fdir, ph, G);
+    Fg[0] = G[0] * dS;
+    Fg[1] = (G[1] * nx + G[2] * tx) * dS;
+    Fg[2] = (G[1] * ny + G[2] * ty) * dS;
+    Fg[3] = G[3] * dS;
+}
+
 template <int TX, int TY>
 constexpr int curv_threads() {
     return (region_faces<TX, TY>() + 63) / 64 * 64;
 }
 
-// Ghost primitives (r, u_x, u_y, T in storage convention) of a far-field face
-// of a cell with primitives P and outward normal (nx, ny): the far-field
-// velocity and temperature where the far-field flow enters, the far-field
-// density where it leaves.
+// Ghost primitives (r, u_x, u_y, T in storage convention) of a far-field
+// face: the free stream (rho = 1, u_inf, T_inf).
 template <typename R, bool DEV>
-__device__ inline void ghost_prims(const CurvGeo &g, const R (&P)[4], R nx, R ny, R (&G)[4]) {
-    const R ux = cg_uinf<R>(g, 0), uy = cg_uinf<R>(g, 1);
-    const bool inflow = ux * nx + uy * ny < (R)0;
-    G[0] = inflow ? P[0] : (DEV ? (R)0 : (R)1);
-    G[1] = inflow ? ux : P[1];
-    G[2] = inflow ? uy : P[2];
-    G[3] = inflow ? cg_Tinf<R>(g) : P[3];
+__device__ inline void ghost_prims(const CurvGeo &g, R (&G)[4]) {
+    G[0] = DEV ? (R)0 : (R)1;
+    G[1] = cg_uinf<R>(g, 0);
+    G[2] = cg_uinf<R>(g, 1);
+    G[3] = cg_Tinf<R>(g);
 }
 
 template <typename R, bool DEV, bool TL, int TX, int TY, bool RES>
@@ -189,7 +226,7 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
                     }
                 } else if (swKind[side] == kFarfield) {
                     R G[4];
-                    ghost_prims<R, DEV>(g, P, so * nxf, so * nyf, G);
+                    ghost_prims<R, DEV>(g, G);
 #pragma unroll
                     for (int p = 0; p < 4; ++p) phi[p] = (R)0.5 * (P[p] + G[p]);
                 } else {
@@ -237,45 +274,20 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
             if (!low_b && !high_b) {
                 Side<R, 2> A, B;
                 const int gL = (loy - 1) * GX + (lox - 1), gR = (hy - 1) * GX + (hx - 1);
-                const R tL = REC(kCfTL), tR = REC(kCfTR);
-                // rotate primitives and gradients into (n, t); shift by the tangential offsets
-                auto fill = [&](Side<R, 2> &S, int cx, int cy, int gidx, R tau) {
-                    const R ux = SP(1, cy, cx), uy = SP(2, cy, cx);
-                    R G[4][2];  // d/dx, d/dy of (r, u_x, u_y, T)
+                R PA[4], PB[4], GA[4][2], GB[4][2];
 #pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-                        G[p][0] = sg[(p * 2 + 0) * GF + gidx];
-                        G[p][1] = sg[(p * 2 + 1) * GF + gidx];
-                    }
-                    const R e[2][2] = {{nxf, nyf}, {txf, tyf}};
-#pragma unroll
-                    for (int k = 0; k < 2; ++k) {
-                        S.g[k][0] = G[0][0] * e[k][0] + G[0][1] * e[k][1];
-                        S.g[k][3] = G[3][0] * e[k][0] + G[3][1] * e[k][1];
-#pragma unroll
-                        for (int qv = 0; qv < 2; ++qv) {  // d_k u_q = e_q . (grad u) e_k
-                            const R gux = G[1][0] * e[k][0] + G[1][1] * e[k][1];
-                            const R guy = G[2][0] * e[k][0] + G[2][1] * e[k][1];
-                            S.g[k][1 + qv] = e[qv][0] * gux + e[qv][1] * guy;
-                        }
-                    }
-                    S.v[0] = SP(0, cy, cx) + S.g[1][0] * tau;
-                    S.v[1] = ux * nxf + uy * nyf + S.g[1][1] * tau;
-                    S.v[2] = ux * txf + uy * tyf + S.g[1][2] * tau;
-                    S.v[3] = SP(3, cy, cx) + S.g[1][3] * tau;
-                };
-                fill(A, lox, loy, gL, tL);
-                fill(B, hx, hy, gR, tR);
-                const R upx = cg_up<R>(g, 0), upy = cg_up<R>(g, 1);
-                const R fdir[2] = {d.force_pred ? upx * nxf + upy * nyf : (R)0,
-                                   d.force_pred ? upx * txf + upy * tyf : (R)0};
-                R G[4];
-                if constexpr (TL) face_flux_tlbfs<R, 2, DEV, true>(A, B, REC(kCfDL), REC(kCfDR), fdir, ph, G);
-                else face_flux<R, 2, DEV, true>(A, B, REC(kCfDL), REC(kCfDR), fdir, ph, G);
-                Fg[0] = G[0] * dS;
-                Fg[1] = (G[1] * nxf + G[2] * txf) * dS;
-                Fg[2] = (G[1] * nyf + G[2] * tyf) * dS;
-                Fg[3] = G[3] * dS;
+                for (int p = 0; p < 4; ++p) {
+                    PA[p] = SP(p, loy, lox);
+                    PB[p] = SP(p, hy, hx);
+                    GA[p][0] = sg[(p * 2 + 0) * GF + gL];
+                    GA[p][1] = sg[(p * 2 + 1) * GF + gL];
+                    GB[p][0] = sg[(p * 2 + 0) * GF + gR];
+                    GB[p][1] = sg[(p * 2 + 1) * GF + gR];
+                }
+                side_in_frame(PA, GA, nxf, nyf, REC(kCfTL), A);
+                side_in_frame(PB, GB, nxf, nyf, REC(kCfTR), B);
+                frame_flux<R, DEV, TL>(A, B, REC(kCfDL), REC(kCfDR), nxf, nyf, cg_up<R>(g, 0), cg_up<R>(g, 1),
+                                       d.force_pred != 0, dS, ph, Fg);
             } else {
                 const int side = isi ? (low_b ? 0 : 1) : (low_b ? 2 : 3);
                 const int wx = low_b ? hx : lox, wy = low_b ? hy : loy;  // the fluid cell
@@ -293,52 +305,35 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
                     Fg[3] = G[3] * dS;
                 } else {
                     // interior-face flux against the mirrored ghost, in the
-                    // frame (so n, so t) with the fluid cell on the low side
+                    // frame of the outward normal so n with the fluid cell on
+                    // the low side; the flux along +n is so times that one
                     const int gidx = (wy - 1) * GX + (wx - 1);
-                    const R nox = so * nxf, noy = so * nyf, tox = so * txf, toy = so * tyf;
+                    const R nox = so * nxf, noy = so * nyf;
                     const R tau = so * (low_b ? REC(kCfTR) : REC(kCfTL));
-                    Side<R, 2> A, B;
+                    const R Pv[4] = {rP, uxP, uyP, TP};
                     R Gd[4][2];
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
                         Gd[p][0] = sg[(p * 2 + 0) * GF + gidx];
                         Gd[p][1] = sg[(p * 2 + 1) * GF + gidx];
                     }
-                    const R e[2][2] = {{nox, noy}, {tox, toy}};
-#pragma unroll
-                    for (int k = 0; k < 2; ++k) {
-                        A.g[k][0] = Gd[0][0] * e[k][0] + Gd[0][1] * e[k][1];
-                        A.g[k][3] = Gd[3][0] * e[k][0] + Gd[3][1] * e[k][1];
-                        const R gux = Gd[1][0] * e[k][0] + Gd[1][1] * e[k][1];
-                        const R guy = Gd[2][0] * e[k][0] + Gd[2][1] * e[k][1];
-#pragma unroll
-                        for (int qv = 0; qv < 2; ++qv) A.g[k][1 + qv] = e[qv][0] * gux + e[qv][1] * guy;
-#pragma unroll
-                        for (int p = 0; p < 4; ++p) B.g[k][p] = (R)0;
-                    }
-                    A.v[0] = rP + A.g[1][0] * tau;
-                    A.v[1] = uxP * nox + uyP * noy + A.g[1][1] * tau;
-                    A.v[2] = uxP * tox + uyP * toy + A.g[1][2] * tau;
-                    A.v[3] = TP + A.g[1][3] * tau;
-                    const R Pv[4] = {rP, uxP, uyP, TP};
+                    Side<R, 2> A, B;
+                    side_in_frame(Pv, Gd, nox, noy, tau, A);
                     R Gh[4];
-                    ghost_prims<R, DEV>(g, Pv, nox, noy, Gh);
+                    ghost_prims<R, DEV>(g, Gh);
                     B.v[0] = Gh[0];
                     B.v[1] = Gh[1] * nox + Gh[2] * noy;
-                    B.v[2] = Gh[1] * tox + Gh[2] * toy;
+                    B.v[2] = -Gh[1] * noy + Gh[2] * nox;
                     B.v[3] = Gh[3];
-                    const R upx = cg_up<R>(g, 0), upy = cg_up<R>(g, 1);
-                    const R fdir[2] = {d.force_pred ? upx * nox + upy * noy : (R)0,
-                                       d.force_pred ? upx * tox + upy * toy : (R)0};
-                    R G[4];
-                    if constexpr (TL) face_flux_tlbfs<R, 2, DEV, true>(A, B, dist, dist, fdir, ph, G);
-                    else face_flux<R, 2, DEV, true>(A, B, dist, dist, fdir, ph, G);
-                    // flux along +n: so times the flux along so n; the momentum
-                    // vector G1 no + G2 to already carries one factor so
-                    Fg[0] = so * G[0] * dS;
-                    Fg[1] = (G[1] * nxf + G[2] * txf) * dS;
-                    Fg[2] = (G[1] * nyf + G[2] * tyf) * dS;
-                    Fg[3] = so * G[3] * dS;
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+#pragma unroll
+                        for (int p = 0; p < 4; ++p) B.g[k][p] = (R)0;
+                    R Fo[4];
+                    frame_flux<R, DEV, TL>(A, B, dist, dist, nox, noy, cg_up<R>(g, 0), cg_up<R>(g, 1),
+                                           d.force_pred != 0, dS, ph, Fo);
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) Fg[p] = so * Fo[p];
                 }
             }
 #pragma unroll
@@ -385,7 +380,7 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
                 acc[1] += an;
                 acc[2] += fabs(Tn - To);
                 acc[3] += Tn;
-                const bool okm = (an * an < 0.25 * kCs2) && (Tn == Tn) && (fabs(Tn) < 1e30);
+                const bool okm = (an * an < d.guard_u2) && (Tn == Tn) && (fabs(Tn) < 1e30);
                 acc[4] += okm ? 0.0 : 1.0;
             }
         }

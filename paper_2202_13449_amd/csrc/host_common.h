@@ -88,6 +88,7 @@ inline int validate(const rtlbfs_mesh *m, const rtlbfs_bc *bc, const rtlbfs_opts
     if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return why = "dtl and dt must be >= 0", RTLBFS_EINVAL;
     if (o.init != RTLBFS_INIT_REST && o.init != RTLBFS_INIT_CONDUCTION) return why = "unknown init", RTLBFS_EINVAL;
     if (o.tile < 0 || o.tile > 9) return why = "opts.tile out of range", RTLBFS_EINVAL;
+    if (!(o.max_mach >= 0.0) || o.max_mach > 10.0) return why = "opts.max_mach out of range", RTLBFS_EINVAL;
     if (o.method != RTLBFS_METHOD_RTLBFS && o.method != RTLBFS_METHOD_TLBFS)
         return why = "unknown opts.method", RTLBFS_EINVAL;
     return RTLBFS_OK;
@@ -222,8 +223,11 @@ inline void pack_geometry(const Problem &p, int precision, std::vector<char> &by
 }
 
 // Everything of the kernel-side Domain except the device pointers.
-inline void fill_domain(const Problem &p, int precision, int force_pred, int round_nearest, Domain &d) {
+inline void fill_domain(const Problem &p, int precision, int force_pred, int round_nearest, double max_mach,
+                        Domain &d) {
     std::memset(&d, 0, sizeof(d));
+    const double mm = max_mach > 0.0 ? max_mach : 0.5;
+    d.guard_u2 = mm * mm * kCs2;  // (Mach * c_s)^2
     d.dim = p.D;
     for (int a = 0; a < 3; ++a) {
         d.n[a] = a < p.D ? p.mesh.n[a] : 1;

@@ -521,7 +521,7 @@ const char *rtlbfs_strerror(int code) {
         case RTLBFS_EINVAL: return "invalid argument";
         case RTLBFS_ENOMEM: return "out of device memory or workspace too small";
         case RTLBFS_EDEVICE: return "HIP runtime error";
-        case RTLBFS_EDIVERGED: return "solution diverged (NaN/Inf or Mach > 0.5)";
+        case RTLBFS_EDIVERGED: return "solution diverged (NaN/Inf or local Mach above opts.max_mach)";
         case RTLBFS_EUNSUPPORTED: return "unsupported request";
         case RTLBFS_ESTATE: return "invalid call order";
         default: return "unknown status";
@@ -586,7 +586,7 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
     h->L = P.L;
     const std::vector<double> &widths = P.widths;
     Domain &d = h->dom;
-    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, d);
+    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, o.max_mach, d);
 
     // Workspace.
     if (workspace) {
@@ -713,7 +713,7 @@ int rtlbfs_sync(rtlbfs_t h) {
     if (!h) return RTLBFS_EINVAL;
     HIP_TRY(h, hipMemcpyAsync(h->host_buf, h->res_out(), kPartials * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    if (h->res_valid && h->host_buf[4] != 0.0) return fail(h, RTLBFS_EDIVERGED, "NaN/Inf or Mach > 0.5 detected");
+    if (h->res_valid && h->host_buf[4] != 0.0) return fail(h, RTLBFS_EDIVERGED, "NaN/Inf or local Mach above opts.max_mach detected");
     return RTLBFS_OK;
 }
 
@@ -881,6 +881,7 @@ int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, doub
     if (o.tile != 0) return reject("opts.tile must be 0 on a body-fitted mesh");
     if (!(nu > 0.0) || !(chi > 0.0) || !(beta_g >= 0.0)) return reject("nu, chi > 0, beta_g >= 0");
     if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return reject("dtl and dt must be >= 0");
+    if (!(o.max_mach >= 0.0) || o.max_mach > 10.0) return reject("opts.max_mach out of range");
     CurvProblem cp;
     std::string why;
     int rc = curv_setup(mesh, bc, cp, why);
@@ -941,7 +942,7 @@ int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, doub
     h->ccy = cp.cy;
     h->carea = cp.area;
     Domain &d = h->dom;
-    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, d);
+    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, o.max_mach, d);
     const bool dev = o.precision != RTLBFS_FP64_PLAIN;
     d.phd.Tref_s = dev ? bc->T_ref - kT0 : bc->T_ref;
     d.phf.Tref_s = (float)d.phd.Tref_s;

@@ -338,7 +338,7 @@ int rtlbfs_batch_create(int count, const rtlbfs_mesh *meshes, const double *Ra, 
     for (int m = 0; m < count; ++m) {
         const Problem &P = h->prob[m];
         Domain &d = h->dom[m];
-        fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, d);
+        fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, o.max_mach, d);
         double *wdev = (double *)(h->ws + L.off_member_w[m]);
         d.w[0] = wdev;
         d.w[1] = wdev + P.mesh.n[0];

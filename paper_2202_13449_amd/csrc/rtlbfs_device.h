@@ -58,6 +58,7 @@ struct Domain {
     Phys<double> phd;
     float Twf[6];        // Tw in FP32
     const double *vol;   // body-fitted meshes: cell areas (device, FP64); null on Cartesian meshes
+    double guard_u2;     // divergence guard: |u|^2 at or above this (Mach max_mach) flags the run
 };
 
 // ------------------------------------------------------------ reductions --

@@ -282,7 +282,7 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
                 acc[2] += fabs(Tn - To);
                 acc[3] += Tn;
                 // divergence guard: NaN/Inf or local Mach |u|/c_s > 0.5
-                const bool okm = (an * an < 0.25 * kCs2) && (Tn == Tn) && (fabs(Tn) < 1e30);
+                const bool okm = (an * an < d.guard_u2) && (Tn == Tn) && (fabs(Tn) < 1e30);
                 acc[4] += okm ? 0.0 : 1.0;
             }
         }

@@ -294,7 +294,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 }
                 const double Tn = (double)Un[4] / rhon + (DEV ? kT0 : 0.0);
                 const double To = (double)TP + (DEV ? kT0 : 0.0);
-                const bool ok = (an < 0.25 * kCs2) && (Tn == Tn) && (fabs(Tn) < 1e30);
+                const bool ok = (an < d.guard_u2) && (Tn == Tn) && (fabs(Tn) < 1e30);
                 an = sqrt(an);
                 ao = sqrt(ao);
                 acc[0] += fabs(an - ao);

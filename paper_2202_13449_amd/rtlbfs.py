@@ -49,6 +49,7 @@ class Opts(C.Structure):
         ("tile", C.c_int),
         ("round_nearest", C.c_int),
         ("method", C.c_int),
+        ("max_mach", C.c_double),
     ]
 
 

@@ -5,6 +5,7 @@
 #include <cstdio>
 
 #include "rtlbfs_device.h"
+#include "curv2d.h"
 
 struct CountedReal {
     double v;
@@ -45,6 +46,32 @@ void count(const char *name) {
     std::printf("%s %ld %ld %ld\n", name, R::adds, R::muls, R::divs);
 }
 
+// One interior face of a body-fitted mesh: both sides rotated into the face
+// frame and shifted along t, the flux, and the rotation back.
+template <bool DEV, bool TL>
+void count_curv(const char *name) {
+    using R = CountedReal;
+    R P[4], Q[4], GP[4][2], GQ[4][2];
+    for (int p = 0; p < 4; ++p) {
+        P[p] = 0.1 * p;
+        Q[p] = 0.2 * p;
+        for (int a = 0; a < 2; ++a) {
+            GP[p][a] = 0.01;
+            GQ[p][a] = 0.02;
+        }
+    }
+    rtlbfs::Phys<R> ph;
+    ph.nu = 0.1; ph.chi = 0.1; ph.dtl = 1.0; ph.tau_f = 0.8; ph.tau_g = 0.9; ph.bg = 1e-3;
+    ph.h = 1.0; ph.inv2h = 0.5; ph.invh2 = 1.0; ph.inv4h2 = 0.25; ph.Tref_s = 0.0;
+    rtlbfs::Side<R, 2> A, B;
+    R F[4];
+    R::adds = R::muls = R::divs = 0;
+    rtlbfs::side_in_frame(P, GP, R(0.6), R(0.8), R(0.1), A);
+    rtlbfs::side_in_frame(Q, GQ, R(0.6), R(0.8), R(-0.1), B);
+    rtlbfs::frame_flux<R, DEV, TL>(A, B, R(0.5), R(0.5), R(0.6), R(0.8), R(0.0), R(1.0), true, R(1.2), ph, F);
+    std::printf("%s %ld %ld %ld\n", name, R::adds, R::muls, R::divs);
+}
+
 int main() {
     count<2, false, false>("2d_plain");
     count<2, true, false>("2d_dev");
@@ -54,5 +81,9 @@ int main() {
     count<2, true, true>("tlbfs_2d_dev");
     count<3, false, true>("tlbfs_3d_plain");
     count<3, true, true>("tlbfs_3d_dev");
+    count_curv<false, false>("curv_2d_plain");
+    count_curv<true, false>("curv_2d_dev");
+    count_curv<false, true>("curv_tlbfs_2d_plain");
+    count_curv<true, true>("curv_tlbfs_2d_dev");
     return 0;
 }

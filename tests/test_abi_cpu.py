@@ -73,7 +73,7 @@ def _create(mesh, bc, Ra=1e3, Pr=0.71, Ma=0.1, opts=None):
 
 
 @pytest.mark.parametrize("case", ["dim", "small", "periodic_pair", "periodic_stretch", "Ra", "Pr", "Ma", "gravity",
-                                  "precision", "kind", "method", "tile"])
+                                  "precision", "kind", "method", "tile", "max_mach"])
 def test_create_rejects_invalid_problems_before_touching_the_device(case):
     mesh = rt.make_mesh(2, (16, 16))
     bc = rt.make_bc((1, 1, 2, 2), (0.5, -0.5, 0, 0), 1)
@@ -103,6 +103,8 @@ def test_create_rejects_invalid_problems_before_touching_the_device(case):
         opts = rt.make_opts(method=2)
     elif case == "tile":
         opts = rt.make_opts(tile=10)
+    elif case == "max_mach":
+        opts = rt.make_opts(max_mach=-0.1)
     rc, h = _create(mesh, bc, Ra, Pr, Ma, opts)
     assert rc == rt.EINVAL and not h.value
 

@@ -10,7 +10,10 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EXPECTED = {"2d_plain": 407, "2d_dev": 428, "3d_plain": 840, "3d_dev": 871,
-            "tlbfs_2d_plain": 414, "tlbfs_2d_dev": 533, "tlbfs_3d_plain": 953, "tlbfs_3d_dev": 1188}
+            "tlbfs_2d_plain": 414, "tlbfs_2d_dev": 533, "tlbfs_3d_plain": 953, "tlbfs_3d_dev": 1188,
+            # one interior face of a body-fitted mesh: frame rotation and tangential shift of both
+            # sides, the flux, the rotation back and the area weighting
+            "curv_2d_plain": 523, "curv_2d_dev": 545, "curv_tlbfs_2d_plain": 530, "curv_tlbfs_2d_dev": 650}
 
 
 @pytest.fixture(scope="module")
