@@ -527,6 +527,126 @@ def steady_bench(rt, torch, steps, warmup, tol=1e-8, max_steps=4_000_000, chunk=
     return res
 
 
+# Body-fitted meshes (Sec. 4.3).  Flops per cell-update of the curvilinear
+# step kernel: two faces (545 FP32-deviation / 523 FP64-plain each, the
+# library's frame functions counted by tests/test_flops_cpu.py) + Eq. 55
+# Gauss gradients over four faces 152 (4 x (4 Eq. 56 values x 4 + normals 4
+# + 4 x 2 x 2 accumulations) + 8 area scalings) + primitives 5 (4) + update
+# and buoyancy 32 (31) + stochastic rounding 24.  Bytes per cell: state read
+# and written (32 / 64) + two face records of 8 values (64 / 128) + 1/dV
+# (4 / 8).
+FLOPS_PER_CELL_CURV = {"f32": 2 * 545 + 152 + 5 + 32 + 24, "f64": 2 * 523 + 152 + 4 + 31}
+BYTES_PER_CELL_CURV = {"f32": 32 + 64 + 4, "f64": 64 + 128 + 8}
+TABLE4 = {0.0: (2.438, 43.65), 100.0: (2.653, 29.91), 800.0: (3.202, 0.0), 1600.0: (3.508, 0.0)}
+
+
+def cylinder_solver(rt, Gr, precision, **opts):
+    """The heated cylinder of Sec. 4.3 on its 450 x 300 O-mesh (lengths in
+    units of the first cell, D = 1/0.003): Re = 20 and Pr = 0.7 give nu and
+    chi from u_inf = 0.1 c_s (Eq. 70), Gr gives beta g (Eq. 71, dT = 1);
+    free stream along +y against gravity, T_wall = 1, T_inf = T_ref = 0.
+    The buoyant plume reaches |u| ~ 0.3 at Gr = 1600, so the divergence
+    guard sits at Mach 0.9."""
+    from paper_2202_13449_amd.workloads import CYLINDER, cylinder_mesh
+
+    x, y, D = cylinder_mesh()
+    u_inf = CYLINDER["u_inf_cs"] * (1.0 / 3.0) ** 0.5
+    nu = u_inf * D / CYLINDER["Re"]
+    chi = nu / CYLINDER["Pr"]
+    s = rt.CurvSolver(np.array(x), np.array(y), (rt.PERIODIC, rt.PERIODIC, rt.WALL_ISOTHERMAL, rt.FARFIELD),
+                      Tw=(0.0, 0.0, CYLINDER["T_wall"], 0.0), up=(0.0, 1.0), T_ref=CYLINDER["T_inf"],
+                      u_inf=(0.0, u_inf), T_inf=CYLINDER["T_inf"], nu=nu, chi=chi, beta_g=Gr * nu * nu / D ** 3,
+                      precision=precision, max_mach=0.9, **opts)
+    return s, D, u_inf
+
+
+def cylinder_nu_and_separation(s):
+    """Eq. 73 average Nusselt number (dT = 1) and the separation angle in
+    degrees from the rear stagnation point: where the tangential velocity of
+    the first cell layer changes sign on the half of the cylinder from the
+    front (theta = -90 deg) to the rear (+90 deg) stagnation point; 0 when
+    the flow stays attached."""
+    q, _ = s.wall_heat(2)
+    ni = s.shape[0]
+    cx, cy, _ = s.geometry()
+    th = np.arctan2(cy[:ni], cx[:ni])
+    ut = -s.field(1)[:ni] * np.sin(th) + s.field(2)[:ni] * np.cos(th)
+    half = np.where((th > -np.pi / 2) & (th < np.pi / 2))[0]
+    half = half[np.argsort(th[half])]
+    v, t = ut[half], th[half]
+    neg = np.where(v < 0.0)[0]
+    sep = 0.0
+    if len(neg) and neg[0] > 0:
+        k = neg[0]
+        ts = t[k - 1] + (t[k] - t[k - 1]) * v[k - 1] / (v[k - 1] - v[k])
+        sep = 90.0 - float(np.degrees(ts))
+    return q / np.pi, sep
+
+
+def cylinder_bench(rt, torch, steps, warmup):
+    """Throughput of the body-fitted step kernel on the Sec. 4.3 mesh
+    (135,000 cells), Gr = 100, FP32 deviation and FP64 plain, with the
+    reductions moved aside (residual once per KERNEL_CHUNK steps, no mass
+    fix); roofline of the FP32 kernel against the FP32 vector peak."""
+    out = {"workload": "cylinder 450x300 O-mesh Re=20 Gr=100 (Sec. 4.3)", "cells": 450 * 300}
+    for name, prec, key in (("fp32_dev", rt.FP32_DEV, "f32"), ("fp64_plain", rt.FP64_PLAIN, "f64")):
+        s, _, _ = cylinder_solver(rt, 100.0, prec, residual_every=KERNEL_CHUNK, mass_fix_every=-1)
+        s.step(max(warmup, KERNEL_CHUNK))
+        s.sync()
+        n = max(KERNEL_CHUNK, steps - steps % KERNEL_CHUNK)
+        ms = timed(torch, s, n)
+        cells = s.cells
+        tf = FLOPS_PER_CELL_CURV[key] * cells / (ms * 1e-3) / 1e12
+        peak = FP32_VECTOR_PEAK_TFLOPS if key == "f32" else FP64_VECTOR_PEAK_TFLOPS
+        out[name] = {"ms_per_step": ms, "value": cells / (ms * 1e-3), "kernel_us": ms * 1e3, "tflops": tf,
+                     "frac": tf / peak, "peak": peak, "flops_per_cell": FLOPS_PER_CELL_CURV[key],
+                     "bytes_per_cell": BYTES_PER_CELL_CURV[key],
+                     "hbm_gbs": BYTES_PER_CELL_CURV[key] * cells / (ms * 1e-3) / 1e9}
+        if key == "f32":
+            out[name]["frac_nonpacked"] = tf / FP32_NONPACKED_PEAK_TFLOPS
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def cylinder_table4_bench(rt, torch, steps, warmup, chunk=200_000, max_steps=4_000_000, window=5):
+    """Sec. 4.3, Table 4: each Gr from the free stream, FP32 deviation
+    storage, until the Eq. 73 Nusselt number moves by less than 2e-5
+    relative over `chunk` steps (at most max_steps); the reported values are
+    the means over the last `window` samples.  Gr = 1600 drifts slowly
+    instead of settling (heat and mass collect where the buoyant plume meets
+    the far-field ghosts), so its window is taken at t* = t u_inf / D in
+    [25, 45], a plateau before the drift sets in; its final value is
+    reported beside it."""
+    rows = {}
+    for Gr, (nu_ref, sep_ref) in TABLE4.items():
+        s, D, u_inf = cylinder_solver(rt, Gr, rt.FP32_DEV, residual_every=1000)
+        dt = s.info.dt
+        hist = []
+        done = 0
+        t0 = time.perf_counter()
+        while done < max_steps:
+            s.step(chunk)
+            done += chunk
+            nu, sep = cylinder_nu_and_separation(s)
+            hist.append((done * dt * u_inf / D, nu, sep))
+            if Gr < 1600.0 and len(hist) > window and abs(hist[-1][1] - hist[-2][1]) < 2e-5 * nu:
+                break
+            if Gr >= 1600.0 and hist[-1][0] > 45.0:
+                break
+        sel = [h for h in hist if 25.0 <= h[0] <= 45.0] if Gr >= 1600.0 else hist[-window:]
+        nu_m = float(np.mean([h[1] for h in sel]))
+        sep_m = float(np.mean([h[2] for h in sel]))
+        rows[str(int(Gr))] = {"Nu": nu_m, "Nu_paper": nu_ref, "Nu_rel_err": abs(nu_m - nu_ref) / nu_ref,
+                              "theta_s": sep_m, "theta_s_paper": sep_ref, "steps": done, "t_star": hist[-1][0],
+                              "final": {"Nu": hist[-1][1], "theta_s": hist[-1][2]},
+                              "residual": s.residual(), "seconds": time.perf_counter() - t0}
+        print(json.dumps({"Gr": Gr, **rows[str(int(Gr))]}), flush=True)
+        del s
+        torch.cuda.empty_cache()
+    return {"workload": "cylinder Table 4 (Re=20, Pr=0.7, Gr 0/100/800/1600), FP32 deviation", "rows": rows}
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle, as written, on a bounded sample of the same workload."""
     from oracle import Oracle, OracleConfig, physics_from_ra, mesh_nodes
@@ -561,12 +681,13 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
     ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods",
-                                                           "stability"],
+                                                           "stability", "cylinder", "cylinder_table4"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
                          "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
                          "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5; "
                          "hill: the Gaussian-hill convergence study of Sec. 4.1; methods: RTLBFS vs TLBFS step cost; "
-                         "stability: the stability maps of Figs. 4-5 as batched runs")
+                         "stability: the stability maps of Figs. 4-5 as batched runs; cylinder: the body-fitted "
+                         "step on the 450x300 O-mesh of Sec. 4.3; cylinder_table4: Table 4, Gr 0..1600")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -596,7 +717,8 @@ def main():
     if args.workload != "cavity256":
         fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,
               "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench,
-              "stability": stability_bench}[args.workload]
+              "stability": stability_bench, "cylinder": cylinder_bench,
+              "cylinder_table4": cylinder_table4_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE

@@ -165,3 +165,58 @@ def test_ra1e8_on_a_10x10_mesh_stays_bounded():
     """Sec. 3.3, Fig. 5: with dtl = 1, Ra = 1e8 stays stable even on 10^2."""
     for method in (rt.METHOD_RTLBFS, rt.METHOD_TLBFS):
         assert not _stability_flags([(10, 1e8), (20, 1e8)], 1.0, method, 100_000).any()
+
+
+def _table4():
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table4_cylinder.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            g, nu, sep = (float(t) for t in line.split())
+            rows[g] = (nu, sep)
+    return rows
+
+
+def _cylinder_nu_sep(s, ni):
+    """Eq. 73 (dT = 1) and the separation angle from the rear stagnation
+    point, where the first-layer tangential velocity changes sign between the
+    front (theta = -90 deg) and rear (+90 deg) stagnation points."""
+    q, _ = s.wall_heat(2)
+    cx, cy, _ = s.geometry()
+    th = np.arctan2(cy[:ni], cx[:ni])
+    ut = -s.field(1)[:ni] * np.sin(th) + s.field(2)[:ni] * np.cos(th)
+    half = np.where((th > -np.pi / 2) & (th < np.pi / 2))[0]
+    half = half[np.argsort(th[half])]
+    v, t = ut[half], th[half]
+    neg = np.where(v < 0.0)[0]
+    if len(neg) == 0:
+        return q / np.pi, 0.0
+    k = neg[0]
+    ts = t[k - 1] + (t[k] - t[k - 1]) * v[k - 1] / (v[k - 1] - v[k])
+    return q / np.pi, 90.0 - float(np.degrees(ts))
+
+
+@pytest.mark.parametrize("Gr", [0.0, 100.0])
+def test_heated_cylinder_matches_table4(Gr):
+    """Sec. 4.3: mixed convection at Re = 20, Pr = 0.7 on the 450 x 300
+    O-mesh (first cell 0.003 D, far field at 52.5 D), FP32 deviation storage,
+    run from the free stream to steady state (2.6 million steps, t u_inf / D
+    about 50).  Eq. 73 Nusselt number within 0.5% of the printed 'Present'
+    value; separation angle within 0.6 deg (the three published values spread
+    over 0.4 deg at Gr = 100)."""
+    from paper_2202_13449_amd.workloads import CYLINDER, cylinder_mesh
+
+    nu_ref, sep_ref = _table4()[Gr]
+    x, y, D = cylinder_mesh()
+    u_inf = CYLINDER["u_inf_cs"] * np.sqrt(1.0 / 3.0)
+    nu = u_inf * D / CYLINDER["Re"]
+    s = rt.CurvSolver(np.array(x), np.array(y), (rt.PERIODIC, rt.PERIODIC, rt.WALL_ISOTHERMAL, rt.FARFIELD),
+                      Tw=(0, 0, 1.0, 0), up=(0.0, 1.0), T_ref=0.0, u_inf=(0.0, u_inf), T_inf=0.0, nu=nu,
+                      chi=nu / CYLINDER["Pr"], beta_g=Gr * nu * nu / D ** 3, precision=rt.FP32_DEV,
+                      residual_every=1000, max_mach=0.9)
+    s.step(2_600_000)
+    Nu, sep = _cylinder_nu_sep(s, 450)
+    assert abs(Nu - nu_ref) <= 0.005 * nu_ref, (Nu, nu_ref)
+    assert abs(sep - sep_ref) <= 0.6, (sep, sep_ref)
+    assert max(s.residual()) < 1e-6
