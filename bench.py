@@ -61,8 +61,10 @@ def kernel_sources_sha256() -> str:
             h.update(name.encode() + b"\0" + f.read())
     with open(os.path.join(CSRC, "rtlbfs_api.hip")) as f:
         api = f.read()
-    m = re.search(r"template <typename R, bool DEV, int TX, int TY, bool RES>\n__global__.*?\n}\n", api, re.S)
-    h.update(b"k_step2d\0" + (m.group(0).encode() if m else b""))
+    m = re.search(r"template <[^\n]*>\n__global__[^\n]*k_step2d\(.*?\n}\n", api, re.S)
+    if not m:
+        raise RuntimeError("k_step2d wrapper not found in rtlbfs_api.hip")
+    h.update(b"k_step2d\0" + m.group(0).encode())
     with open(os.path.join(ROOT, "paper_2202_13449_amd", "build.py"), "rb") as f:
         h.update(b"build.py\0" + f.read())
     return h.hexdigest()
