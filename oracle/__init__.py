@@ -8,4 +8,4 @@ from .oracle import (  # noqa: F401
     INIT_CONDUCTION, INIT_REST, PERIODIC, RTLBFS, TLBFS, WALL_ADIABATIC, WALL_ISOTHERMAL, Oracle, OracleConfig,
     face_flux, face_flux_frame,
     mesh_nodes, physics_from_ra, splitmix_uniform)
-from .curvilinear import FARFIELD, CurvConfig, CurvOracle  # noqa: F401,E402
+from .curvilinear import FARFIELD, Curv3Config, Curv3Oracle, CurvConfig, CurvOracle  # noqa: F401,E402

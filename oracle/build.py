@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rtlbfs_oracle.c")
-SRCS = [SRC, os.path.join(HERE, "curv_oracle.c")]
+SRCS = [SRC, os.path.join(HERE, "curv_oracle.c"), os.path.join(HERE, "curv3_oracle.c")]
 LIB = os.path.join(HERE, "librtlbfs_oracle.so")
 
 

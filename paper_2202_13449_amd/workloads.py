@@ -98,3 +98,40 @@ def cylinder_mesh(ni: int = 450, nj: int = 300, far: float = 52.5, first: float 
     D = 1.0 / first
     x, y = o_mesh(ni, nj, 0.5 * D, far * D, 1.0, theta0=-0.5 * math.pi)
     return x, y, D
+
+
+def annulus_wedge(nr: int, nth: int, nz: int, r_in: float, r_out: float, height: float, dtheta: float):
+    """Vertices of a wedge of a concentric annulus: i runs outward (uniform
+    in r), j around z over nth cells of angle dtheta (symmetric about the x
+    axis), k up (uniform in z).  Vertex layer j = nth is layer 0 rotated by
+    nth * dtheta about z.  Returns x, y, z as nested lists
+    (nz + 1) x (nth + 1) x (nr + 1)."""
+    r = [r_in + (r_out - r_in) * i / nr for i in range(nr + 1)]
+    th = [(j - 0.5 * nth) * dtheta for j in range(nth + 1)]
+    zz = [height * k / nz for k in range(nz + 1)]
+    x = [[[ri * math.cos(t) for ri in r] for t in th] for _ in zz]
+    y = [[[ri * math.sin(t) for ri in r] for t in th] for _ in zz]
+    z = [[[zk for _ in r] for _ in th] for zk in zz]
+    return x, y, z
+
+
+# Sec. 4.5: natural convection in a concentric annulus, Ar = R_o/R_i = 2,
+# eta = H/(R_o - R_i) = 2, Pr = 0.71, V_c = 0.1, Ra in {1e4, 1e5}, inner
+# wall T_i = 1, outer T_o = 0, top and bottom adiabatic; 120 x 1 x 240
+# cells (r, theta, z), one azimuthal layer closed by rotational periodicity.
+# Lengths in units of the radial cell: R_i = 120, R_o = 240, H = 240; the
+# wedge angle (not given) is taken as 1/120 rad, so the cells at the inner
+# wall are cubes.
+ANNULUS = dict(nr=120, nth=1, nz=240, Ar=2.0, eta=2.0, Pr=0.71, Vc=0.1, Ra=(1e4, 1e5))
+
+
+def annulus_mesh(nr: int = 120, nz: int = 240, Ar: float = 2.0, eta: float = 2.0, nth: int = 1):
+    """The Sec. 4.5 wedge: radial gap of nr unit cells, R_i = nr / (Ar - 1),
+    height eta * nr, wedge angle 1/R_i per azimuthal cell.  Returns
+    (x, y, z, R_i, R_o, H, dtheta)."""
+    gap = float(nr)
+    r_in = gap / (Ar - 1.0)
+    H = eta * gap
+    dth = 1.0 / r_in
+    x, y, z = annulus_wedge(nr, nth, nz, r_in, r_in + gap, H, dth)
+    return x, y, z, r_in, r_in + gap, H, dth

@@ -86,3 +86,29 @@ def o_mesh(ni, nj, r_in, r_out, first, theta0=0.0):
 
     x, y = _o(ni, nj, r_in, r_out, first, theta0)
     return np.array(x), np.array(y)
+
+
+def cartesian_vertices3(xn, yn, zn):
+    """Vertex arrays (nk + 1, nj + 1, ni + 1) of a 3D Cartesian mesh."""
+    Z, Y, X = np.meshgrid(np.asarray(zn, float), np.asarray(yn, float), np.asarray(xn, float), indexing="ij")
+    return X.copy(), Y.copy(), Z.copy()
+
+
+def wavy_vertices3(xn, yn, zn, amp):
+    """A 3D Cartesian mesh bent by smooth displacements that vanish on the
+    box faces' normal components (the outer boundary stays a box)."""
+    X, Y, Z = cartesian_vertices3(xn, yn, zn)
+    L = [X.max() - X.min(), Y.max() - Y.min(), Z.max() - Z.min()]
+    sx = np.sin(np.pi * (X - X.min()) / L[0])
+    sy = np.sin(np.pi * (Y - Y.min()) / L[1])
+    sz = np.sin(np.pi * (Z - Z.min()) / L[2])
+    b = sx * sy * sz
+    return (X + amp * L[0] * b * np.cos(2 * np.pi * (Y - Y.min()) / L[1]),
+            Y + amp * L[1] * b * np.sin(2 * np.pi * (Z - Z.min()) / L[2]),
+            Z + amp * L[2] * b * np.cos(2 * np.pi * (X - X.min()) / L[0]))
+
+
+def annulus_wedge(nr, nth, nz, r_in, r_out, height, dtheta):
+    from paper_2202_13449_amd.workloads import annulus_wedge as _w
+
+    return tuple(np.array(v) for v in _w(nr, nth, nz, r_in, r_out, height, dtheta))
