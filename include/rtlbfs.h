@@ -287,13 +287,67 @@ int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, doub
  * from these: Eq. 73 on a cylinder is out[0] / (pi dT), the average of
  * Eq. 78 on a cylinder of radius R and height H is R out[0] / (out[1] dT)
  * per unit height.  EINVAL if the side is not an isothermal wall,
- * EUNSUPPORTED on a Cartesian handle. */
+ * EUNSUPPORTED on a Cartesian handle.  Also for 3D body-fitted handles
+ * (sides 0..5). */
 int rtlbfs_wall_heat(rtlbfs_t h, int side, double out[2]);
 
 /* Geometry the library derived for a body-fitted mesh (host only): cell
  * centroids and areas, `count` >= cells values each (any pointer may be
  * NULL).  EUNSUPPORTED on a Cartesian handle. */
 int rtlbfs_curv_cells(rtlbfs_t h, double *host_cx, double *host_cy, double *host_area, size_t count);
+
+/* ------------------------------------------------- body-fitted 3D meshes -- */
+/* The step on a 3D structured curvilinear hexahedral mesh, the setting of
+ * Sec. 4.5 (a concentric annulus run with one azimuthal cell layer).  Each
+ * face carries its unit normal n (from the diagonal cross product of its four
+ * corners), a tangent t1 (its first edge without the normal part) and
+ * t2 = n x t1; the D3Q19 lattice of the predictor is aligned with them; the
+ * face centre is the mean of the corners; cell centroids and volumes come
+ * from a tetrahedral split.  Cells are stored i-fastest: index
+ * = i + n0*(j + n1*k), fields rho, u_x, u_y, u_z, T as on Cartesian 3D meshes.
+ *
+ * A periodic pair of sides may be closed by a rotation about the z axis
+ * (rot[axis] radians): vertex layer n equals layer 0 rotated by rot, and the
+ * neighbour across the pair is the cell on the other side, rotated with its
+ * velocity and velocity gradient.  With one cell along that axis this is the
+ * single-layer wedge of an axisymmetric problem.  Walls as on 2D body-fitted
+ * meshes; no far-field sides in 3D. */
+typedef struct {
+    int n[3];        /* cells along i, j, k; >= 2 on walled axes, >= 1 on periodic ones */
+    const double *x; /* host vertex coordinates, (n[2]+1)*(n[1]+1)*(n[0]+1) values each,
+                        vertex (i, j, k) at ((k*(n[1]+1) + j)*(n[0]+1) + i); cell (i, j, k)
+                        spans vertices i..i+1, j..j+1, k..k+1; one orientation for all cells.
+                        Read during create only. */
+    const double *y;
+    const double *z;
+} rtlbfs_curv3_mesh;
+
+typedef struct {
+    int kind[6];    /* sides i-, i+, j-, j+, k-, k+: RTLBFS_PERIODIC (in pairs),
+                       RTLBFS_WALL_ISOTHERMAL or RTLBFS_WALL_ADIABATIC */
+    double rot[3];  /* rotation about z closing each periodic axis (radians, |rot| <= 3.2), 0 otherwise */
+    double Tw[6];   /* absolute temperature of isothermal walls */
+    double up[3];   /* unit vector against gravity, or zero for no buoyancy */
+    double T_ref;   /* absolute reference temperature of the buoyancy force; also the initial T */
+} rtlbfs_curv3_bc;
+
+/* Device workspace for a 3D body-fitted mesh (bytes); 0 for invalid sizes. */
+size_t rtlbfs_curv3_workspace_bytes(const rtlbfs_curv3_mesh *mesh, const rtlbfs_opts *opts);
+
+/* Create a solver on a 3D body-fitted mesh; nu, chi, beta_g given directly.
+ * The state starts at rest with rho = 1 and T = T_ref (+ opts->noise_amp
+ * noise).  Options, workspace, stream and errors as for rtlbfs_curv_create
+ * (opts->tile must be 0).  The handle works with the single-domain entry
+ * points and rtlbfs_wall_heat (sides 0..5); rtlbfs_nusselt returns
+ * RTLBFS_EUNSUPPORTED. */
+int rtlbfs_curv3_create(const rtlbfs_curv3_mesh *mesh, double nu, double chi, double beta_g,
+                        const rtlbfs_curv3_bc *bc, const rtlbfs_opts *opts, void *hip_stream, void *workspace,
+                        size_t ws_bytes, rtlbfs_t *out);
+
+/* Centroids and volumes the library derived for a 3D body-fitted mesh (host
+ * only; any pointer may be NULL).  EUNSUPPORTED on other handles. */
+int rtlbfs_curv3_cells(rtlbfs_t h, double *host_cx, double *host_cy, double *host_cz, double *host_vol,
+                       size_t count);
 
 /* ----------------------------------------------------------- batched -- */
 /* Many independent 2D domains advanced together: one kernel launch per step

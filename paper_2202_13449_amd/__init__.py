@@ -6,6 +6,6 @@ The compute path is the HIP library librtlbfs.so (C ABI in include/rtlbfs.h);
 from .rtlbfs import (  # noqa: F401
     EDIVERGED, EINVAL, EUNSUPPORTED, FARFIELD, FP32_DEV, FP64_DEV, FP64_PLAIN, INIT_CONDUCTION, INIT_REST,
     METHOD_RTLBFS, METHOD_TLBFS, OK, PERIODIC,
-    WALL_ADIABATIC, WALL_ISOTHERMAL, Batch, CurvSolver, RtlbfsError, Solver, load_library, make_bc, make_mesh,
+    WALL_ADIABATIC, WALL_ISOTHERMAL, Batch, Curv3Solver, CurvSolver, RtlbfsError, Solver, load_library, make_bc, make_mesh,
     make_opts,
     mesh_nodes, strerror)

@@ -1,0 +1,425 @@
+// curv3d.h -- the RTLBFS time step on a 3D body-fitted (structured
+// curvilinear) hexahedral mesh, the setting of Sec. 4.5: a concentric
+// annulus run with a single azimuthal cell layer, whose two azimuthal sides
+// form a periodic pair closed by a rotation about z.
+//
+// Each face carries its unit normal n, a tangent t1 (the face's first edge
+// without its normal part) and t2 = n x t1; the D3Q19 lattice of Fig. 1 is
+// aligned with (n, t1, t2).  A step is three launches over HBM buffers, one
+// thread per item (the meshes of this setting are small, and each pass is a
+// plain streaming loop):
+//   k_c3_grad    per cell: primitives and Eq. 55 gradients, sum over the six
+//                faces of phi_S S_out / dV with Eq. 56 face values;
+//   k_c3_flux    per face: the interior-face flux in the face frame (the
+//                Eq. 29 values of a side whose centre lies off the normal are
+//                shifted by the tangential gradients times the offsets) or
+//                the wall closure; area-weighted, global components;
+//   k_c3_update  per cell: divergence, buoyancy along `up`, forward Euler,
+//                stochastic rounding of the FP32 state, Eq. 65 partials.
+// Across a periodic side the neighbour is the image of the cell on the other
+// side, rotated by -alpha (low side) or +alpha (high side) about z: its
+// velocity as a vector, its velocity gradient as R G R^T.  Every face,
+// including both faces of a periodic pair, computes its own flux.
+//
+// Face records (SoA, kernel precision), axis-a faces at index
+// (k*(n1 + [a=1]) + j)*(n0 + [a=0]) + i, i.e. the vertex numbering with the
+// face's own axis extended.
+#pragma once
+
+#include "rtlbfs_device.h"
+
+namespace rtlbfs {
+
+// n (3), t1 (3), dS, then for the low cell L and the high cell R:
+// dL = (x_S - x_L).n, tL1/tL2 = (x_S - x_L).t1/t2, dR = (x_R - x_S).n,
+// tR1/tR2 = (x_S - x_R).t1/t2, and the Eq. 56 weight wL of the low cell's
+// value.  Images across periodic sides enter with their rotated centroids;
+// a wall face stores the interior cell's normal distance in dL and dR.
+enum : int {
+    kC3Nx = 0, kC3Ny, kC3Nz, kC3T1x, kC3T1y, kC3T1z, kC3DS, kC3DL, kC3TL1, kC3TL2, kC3DR, kC3TR1, kC3TR2, kC3WL,
+    kC3Fields
+};
+
+struct Curv3Geo {
+    const void *f[3];      // face records per axis (kernel precision), kC3Fields fields each
+    int64_t sf[3];         // face counts per axis (field strides)
+    const void *inv_vol;   // 1 / dV per cell
+    void *prim;            // scratch: 5 primitives per cell (field-major, stride = cells)
+    void *grad;            // scratch: 15 gradients per cell, [p * 3 + axis]
+    void *flux;            // scratch: 5 area-weighted fluxes per face, faces of the three axes concatenated
+    int64_t nfaces;        // F0 + F1 + F2
+    double rc[3], rs[3];   // cos, sin of the closing rotation of each periodic axis (1, 0 if none)
+    double up[3];          // unit vector against gravity (0 if no buoyancy)
+    float upf[3];
+};
+
+template <typename R>
+__device__ inline R c3_up(const Curv3Geo &g, int a) {
+    if constexpr (sizeof(R) == 4) return g.upf[a];
+    else return g.up[a];
+}
+
+// Rotation about z by the angle with cosine c, sine s: v -> R v.
+template <typename R>
+__host__ __device__ inline void rot_z(R c, R s, R (&v)[3]) {
+    const R x = c * v[0] - s * v[1], y = s * v[0] + c * v[1];
+    v[0] = x;
+    v[1] = y;
+}
+
+// One side of a face in the frame e[0] = n, e[1] = t1, e[2] = t2: primitives
+// P = (r, u_x, u_y, u_z, T) and gradients G[p][axis] of a cell, rotated, and
+// shifted by the tangential gradients times tau1, tau2.
+template <typename R>
+__host__ __device__ inline void side_in_frame3(const R (&P)[5], const R (&G)[5][3], const R (&e)[3][3], R tau1,
+                                               R tau2, Side<R, 3> &S) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        S.g[k][0] = G[0][0] * e[k][0] + G[0][1] * e[k][1] + G[0][2] * e[k][2];
+        S.g[k][4] = G[4][0] * e[k][0] + G[4][1] * e[k][1] + G[4][2] * e[k][2];
+        R gu[3];  // d_k u_x, d_k u_y, d_k u_z
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gu[a] = G[1 + a][0] * e[k][0] + G[1 + a][1] * e[k][1] + G[1 + a][2] * e[k][2];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S.g[k][1 + q] = e[q][0] * gu[0] + e[q][1] * gu[1] + e[q][2] * gu[2];
+    }
+    S.v[0] = P[0];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) S.v[1 + q] = P[1] * e[q][0] + P[2] * e[q][1] + P[3] * e[q][2];
+    S.v[4] = P[4];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) S.v[p] += S.g[1][p] * tau1 + S.g[2][p] * tau2;
+}
+
+// Interior-face flux (RTLBFS, or TLBFS when TL) along +n times the face
+// area, momentum back in global components.
+template <typename R, bool DEV, bool TL>
+__host__ __device__ inline void frame_flux3(const Side<R, 3> &A, const Side<R, 3> &B, R dL, R dR, const R (&e)[3][3],
+                                            const R (&up)[3], bool fp, R dS, const Phys<R> &ph, R (&F)[5]) {
+    R fdir[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) fdir[q] = fp ? up[0] * e[q][0] + up[1] * e[q][1] + up[2] * e[q][2] : (R)0;
+    R G[5];
+    if constexpr (TL) face_flux_tlbfs<R, 3, DEV, true>(A, B, dL, dR, fdir, ph, G);
+    else face_flux<R, 3, DEV, true>(A, B, dL, dR, fdir, ph, G);
+    F[0] = G[0] * dS;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[1 + a] = (G[1] * e[0][a] + G[2] * e[1][a] + G[3] * e[2][a]) * dS;
+    F[4] = G[4] * dS;
+}
+
+__device__ inline int64_t c3_cell(const Domain &d, int i, int j, int k) {
+    return ((int64_t)k * d.n[1] + j) * d.n[0] + i;
+}
+
+__device__ inline int64_t c3_face(const Domain &d, int a, int i, int j, int k) {
+    return ((int64_t)k * (d.n[1] + (a == 1)) + j) * (d.n[0] + (a == 0)) + i;
+}
+
+// Neighbour of cell q (index triple) across its face on `axis`, side hi:
+// the mesh cell and the sine of its image rotation (cosine in *c); -1 at a
+// wall.
+__device__ inline int64_t c3_neighbour(const Domain &d, const Curv3Geo &g, const int (&q)[3], int axis, int hi,
+                                       double &c, double &s) {
+    int r[3] = {q[0], q[1], q[2]};
+    r[axis] += hi ? 1 : -1;
+    c = 1.0;
+    s = 0.0;
+    if (r[axis] < 0 || r[axis] >= d.n[axis]) {
+        if (!d.periodic[axis]) return -1;
+        c = g.rc[axis];
+        s = hi ? g.rs[axis] : -g.rs[axis];
+        r[axis] = r[axis] < 0 ? r[axis] + d.n[axis] : r[axis] - d.n[axis];
+    }
+    return c3_cell(d, r[0], r[1], r[2]);
+}
+
+template <typename R, bool DEV>
+__device__ inline void c3_prims(const Domain &d, const R *__restrict__ U, int64_t c, R (&P)[5]) {
+    const int64_t N = d.fstride;
+    const R r = U[c];
+    const R inv = recip<R>(DEV ? (R)1 + r : r);
+    P[0] = r;
+#pragma unroll
+    for (int p = 1; p < 5; ++p) P[p] = U[p * N + c] * inv;
+}
+
+template <typename R, bool DEV>
+__global__ void __launch_bounds__(256) k_c3_grad(Domain d, Curv3Geo g, const R *__restrict__ U) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= d.cells) return;
+    const int i = (int)(c % d.n[0]), j = (int)((c / d.n[0]) % d.n[1]), k = (int)(c / ((int64_t)d.n[0] * d.n[1]));
+    const int q[3] = {i, j, k};
+    R P[5];
+    c3_prims<R, DEV>(d, U, c, P);
+    R acc[5][3];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) acc[p][0] = acc[p][1] = acc[p][2] = (R)0;
+    for (int a = 0; a < 3; ++a)
+        for (int hi = 0; hi < 2; ++hi) {
+            int fq[3] = {i, j, k};
+            fq[a] += hi;
+            const R *rec = (const R *)g.f[a] + c3_face(d, a, fq[0], fq[1], fq[2]);
+            const int64_t st = g.sf[a];
+            const R so = hi ? (R)1 : (R)-1;
+            const R sx = so * rec[kC3Nx * st] * rec[kC3DS * st], sy = so * rec[kC3Ny * st] * rec[kC3DS * st];
+            const R sz = so * rec[kC3Nz * st] * rec[kC3DS * st];
+            double cr, sr;
+            const int64_t nb = c3_neighbour(d, g, q, a, hi, cr, sr);
+            R phi[5];
+            if (nb < 0) {
+                const int side = 2 * a + hi;
+                phi[0] = P[0];
+                phi[1] = phi[2] = phi[3] = (R)0;
+                phi[4] = d.kind[side] == kIsothermal ? wall_T<R>(d, side) : P[4];
+            } else {
+                R Q[5];
+                c3_prims<R, DEV>(d, U, nb, Q);
+                R u[3] = {Q[1], Q[2], Q[3]};
+                rot_z<R>((R)cr, (R)sr, u);
+                Q[1] = u[0];
+                Q[2] = u[1];
+                Q[3] = u[2];
+                const R wL = rec[kC3WL * st];
+#pragma unroll
+                for (int p = 0; p < 5; ++p) phi[p] = hi ? wL * P[p] + ((R)1 - wL) * Q[p] : wL * Q[p] + ((R)1 - wL) * P[p];
+            }
+#pragma unroll
+            for (int p = 0; p < 5; ++p) {
+                acc[p][0] += phi[p] * sx;
+                acc[p][1] += phi[p] * sy;
+                acc[p][2] += phi[p] * sz;
+            }
+        }
+    const R iv = ((const R *)g.inv_vol)[c];
+    R *pr = (R *)g.prim, *gr = (R *)g.grad;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        pr[p * d.cells + c] = P[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gr[(p * 3 + a) * d.cells + c] = acc[p][a] * iv;
+    }
+}
+
+// Primitives and gradients of cell c from the scratch buffers, as the image
+// rotated by (cr, sr) about z.
+template <typename R>
+__device__ inline void c3_view(const Domain &d, const Curv3Geo &g, int64_t c, R cr, R sr, R (&P)[5], R (&G)[5][3]) {
+    const R *pr = (const R *)g.prim, *gr = (const R *)g.grad;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        P[p] = pr[p * d.cells + c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) G[p][a] = gr[(p * 3 + a) * d.cells + c];
+    }
+    if (sr == (R)0 && cr == (R)1) return;
+    R u[3] = {P[1], P[2], P[3]};
+    rot_z(cr, sr, u);
+    P[1] = u[0];
+    P[2] = u[1];
+    P[3] = u[2];
+    R g0[3] = {G[0][0], G[0][1], G[0][2]}, g4[3] = {G[4][0], G[4][1], G[4][2]};
+    rot_z(cr, sr, g0);
+    rot_z(cr, sr, g4);
+    // velocity gradient M[a][b] = d_b u_a -> R M R^T: rotate rows, then columns
+    R M[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        R col[3] = {G[1][b], G[2][b], G[3][b]};
+        rot_z(cr, sr, col);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) M[a][b] = col[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R row[3] = {M[a][0], M[a][1], M[a][2]};
+        rot_z(cr, sr, row);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) G[1 + a][b] = row[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        G[0][a] = g0[a];
+        G[4][a] = g4[a];
+    }
+}
+
+template <typename R, bool DEV, bool TL>
+__global__ void __launch_bounds__(256) k_c3_flux(Domain d, Curv3Geo g, const R *__restrict__ U) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.nfaces) return;
+    int a = 0;
+    int64_t f = t;
+    while (a < 2 && f >= g.sf[a]) {
+        f -= g.sf[a];
+        ++a;
+    }
+    const int nx = d.n[0] + (a == 0), ny = d.n[1] + (a == 1);
+    const int q[3] = {(int)(f % nx), (int)((f / nx) % ny), (int)(f / ((int64_t)nx * ny))};
+    const R *rec = (const R *)g.f[a] + f;
+    const int64_t st = g.sf[a];
+    R e[3][3];
+    e[0][0] = rec[kC3Nx * st];
+    e[0][1] = rec[kC3Ny * st];
+    e[0][2] = rec[kC3Nz * st];
+    e[1][0] = rec[kC3T1x * st];
+    e[1][1] = rec[kC3T1y * st];
+    e[1][2] = rec[kC3T1z * st];
+    e[2][0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];  // t2 = n x t1
+    e[2][1] = e[0][2] * e[1][0] - e[0][0] * e[1][2];
+    e[2][2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+    const R dS = rec[kC3DS * st];
+    const Phys<R> &ph = make_phys<R>(d);
+    const int na = d.n[a];
+    const bool per = d.periodic[a];
+    R F[5];
+    if (per || (q[a] > 0 && q[a] < na)) {
+        // low cell (image rotated by -alpha at face 0), high cell (image by +alpha at face n)
+        int lo[3] = {q[0], q[1], q[2]}, hi[3] = {q[0], q[1], q[2]};
+        lo[a] -= 1;
+        R cl = (R)1, sl = (R)0, ch = (R)1, sh = (R)0;
+        if (lo[a] < 0) {
+            lo[a] += na;
+            cl = (R)g.rc[a];
+            sl = -(R)g.rs[a];
+        }
+        if (hi[a] >= na) {
+            hi[a] -= na;
+            ch = (R)g.rc[a];
+            sh = (R)g.rs[a];
+        }
+        R PA[5], PB[5], GA[5][3], GB[5][3];
+        c3_view<R>(d, g, c3_cell(d, lo[0], lo[1], lo[2]), cl, sl, PA, GA);
+        c3_view<R>(d, g, c3_cell(d, hi[0], hi[1], hi[2]), ch, sh, PB, GB);
+        Side<R, 3> A, B;
+        side_in_frame3<R>(PA, GA, e, rec[kC3TL1 * st], rec[kC3TL2 * st], A);
+        side_in_frame3<R>(PB, GB, e, rec[kC3TR1 * st], rec[kC3TR2 * st], B);
+        const R up[3] = {c3_up<R>(g, 0), c3_up<R>(g, 1), c3_up<R>(g, 2)};
+        frame_flux3<R, DEV, TL>(A, B, rec[kC3DL * st], rec[kC3DR * st], e, up, d.force_pred != 0, dS, ph, F);
+    } else {
+        const bool low = q[a] == 0;  // wall on the low side: the fluid cell is the high one
+        int w[3] = {q[0], q[1], q[2]};
+        if (!low) w[a] -= 1;
+        const int64_t c = c3_cell(d, w[0], w[1], w[2]);
+        const int side = 2 * a + (low ? 0 : 1);
+        const int64_t N = d.fstride;
+        const R rP = U[c];
+        const R m[3] = {U[N + c], U[2 * N + c], U[3 * N + c]};
+        R ml[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ml[k] = m[0] * e[k][0] + m[1] * e[k][1] + m[2] * e[k][2];
+        R G[5];
+        wall_flux<R, 3, DEV>(rP, ml, U[4 * N + c], low ? (R)-1 : (R)1, low ? rec[kC3DR * st] : rec[kC3DL * st],
+                             d.kind[side] == kIsothermal, wall_T<R>(d, side), ph, G);
+        F[0] = G[0] * dS;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) F[1 + b] = (G[1] * e[0][b] + G[2] * e[1][b] + G[3] * e[2][b]) * dS;
+        F[4] = G[4] * dS;
+    }
+    R *out = (R *)g.flux;
+#pragma unroll
+    for (int p = 0; p < 5; ++p) out[p * g.nfaces + t] = F[p];
+}
+
+template <typename R, bool DEV, bool RES>
+__global__ void __launch_bounds__(256) k_c3_update(Domain d, Curv3Geo g, const R *__restrict__ Uin,
+                                                   R *__restrict__ Uout, double *__restrict__ parts,
+                                                   const uint32_t *__restrict__ ctr_in, uint32_t *__restrict__ ctr_out) {
+    __shared__ double sred[kPartials * 4];
+    const uint32_t key = *ctr_in;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (c < d.cells) {
+        const int i = (int)(c % d.n[0]), j = (int)((c / d.n[0]) % d.n[1]), k = (int)(c / ((int64_t)d.n[0] * d.n[1]));
+        const int64_t N = d.fstride;
+        const R *fl = (const R *)g.flux;
+        R div[5] = {0, 0, 0, 0, 0};
+        int64_t base = 0;
+        for (int a = 0; a < 3; ++a) {
+            int hq[3] = {i, j, k};
+            hq[a] += 1;
+            const int64_t flo = base + c3_face(d, a, i, j, k), fhi = base + c3_face(d, a, hq[0], hq[1], hq[2]);
+#pragma unroll
+            for (int p = 0; p < 5; ++p) div[p] += fl[p * g.nfaces + flo] - fl[p * g.nfaces + fhi];
+            base += g.sf[a];
+        }
+        const Phys<R> &ph = make_phys<R>(d);
+        const R *pr = (const R *)g.prim;
+        const R rP = pr[c], TP = pr[4 * d.cells + c];
+        const R rhoP = DEV ? (R)1 + rP : rP;
+        const R dtR = ph.dt;
+        const R dt_dV = dtR * ((const R *)g.inv_vol)[c];
+        const R Fb = dtR * ph.bg * rhoP * (TP - ph.Tref_s);
+        R Un[5];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            const R src = (p >= 1 && p <= 3) ? Fb * c3_up<R>(g, p - 1) : (R)0;
+            const R inc = dt_dV * div[p] + src;
+            const R old = Uin[p * N + c];
+            if (sizeof(R) == 4 && d.sround) Un[p] = sr_add(old, inc, sr_hash((uint32_t)c, key * 5u + p));
+            else Un[p] = old + inc;
+            Uout[p * N + c] = Un[p];
+        }
+        if (RES) {
+            const double rn = (double)Un[0];
+            const double rhon = DEV ? 1.0 + rn : rn;
+            double an = 0.0, ao = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double vn = (double)Un[1 + a] / rhon, vo = (double)pr[(1 + a) * d.cells + c];
+                an += vn * vn;
+                ao += vo * vo;
+            }
+            an = sqrt(an);
+            ao = sqrt(ao);
+            const double Tn = (double)Un[4] / rhon + (DEV ? kT0 : 0.0), To = (double)TP + (DEV ? kT0 : 0.0);
+            acc[0] = fabs(an - ao);
+            acc[1] = an;
+            acc[2] = fabs(Tn - To);
+            acc[3] = Tn;
+            acc[4] = (an * an < d.guard_u2) && (Tn == Tn) && (fabs(Tn) < 1e30) ? 0.0 : 1.0;
+        }
+    }
+    if (RES) {
+        block_sums<kPartials>(acc, sred);
+        if (threadIdx.x == 0)
+            for (int m = 0; m < kPartials; ++m) parts[(int64_t)blockIdx.x * kPartials + m] = acc[m];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
+}
+
+// Wall heat of one side: {sum (T_w - T_P)/d dS, sum dS} (single block, FP64
+// records).
+template <typename R, bool DEV>
+__global__ void __launch_bounds__(256) k_c3_wall_heat(Domain d, const double *__restrict__ rec64, int64_t st,
+                                                      const R *__restrict__ U, int side, double Tw_abs,
+                                                      double *__restrict__ out) {
+    __shared__ double sred[2 * 4];
+    const int a = side / 2, hi = side & 1;
+    const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    const int n1 = d.n[b1], n2 = d.n[b2];
+    const int64_t N = d.fstride;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t m = threadIdx.x; m < (int64_t)n1 * n2; m += blockDim.x) {
+        int q[3];
+        q[a] = hi ? d.n[a] : 0;
+        q[b1] = (int)(m % n1);
+        q[b2] = (int)(m / n1);
+        const double *r = rec64 + c3_face(d, a, q[0], q[1], q[2]);
+        int w[3] = {q[0], q[1], q[2]};
+        if (hi) w[a] -= 1;
+        const int64_t c = c3_cell(d, w[0], w[1], w[2]);
+        const double dS = r[kC3DS * st], dist = hi ? r[kC3DL * st] : r[kC3DR * st];
+        const double rr = (double)U[c];
+        const double rho = DEV ? 1.0 + rr : rr;
+        const double TP = (double)U[4 * N + c] / rho + (DEV ? kT0 : 0.0);
+        acc[0] += (Tw_abs - TP) / dist * dS;
+        acc[1] += dS;
+    }
+    block_sums<2>(acc, sred);
+    if (threadIdx.x == 0) {
+        out[0] = acc[0];
+        out[1] = acc[1];
+    }
+}
+
+}  // namespace rtlbfs

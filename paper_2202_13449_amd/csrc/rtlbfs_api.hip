@@ -19,6 +19,8 @@
 #include "host_common.h"
 #include "curv2d.h"
 #include "curv_host.h"
+#include "curv3d.h"
+#include "curv3_host.h"
 
 using namespace rtlbfs;
 using namespace rtlbfs::host;
@@ -80,7 +82,6 @@ struct Tile2 {
 constexpr Tile2 kTiles2[] = {{32, 8, 1, 0},  {16, 16, 1, 1}, {64, 4, 1, 2}, {16, 8, 1, 3}, {8, 8, 1, 4},
                              {16, 16, 2, 1}, {32, 8, 2, 0},  {16, 8, 2, 3}, {8, 8, 2, 4}};
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
-constexpr int kTX2 = 32, kTY2 = 8;             // largest 2D tile (sizes the partials buffer)
 constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per face)
 constexpr int kRedBlocks = 512;                // blocks of the diagnostics kernels
 
@@ -154,9 +155,14 @@ struct rtlbfs_handle {
     CurvGeo cg{};
     const double *fi64 = nullptr, *fj64 = nullptr;  // FP64 face records (diagnostics)
     int64_t nfi = 0, nfj = 0;
-    int ckind[4] = {0, 0, 0, 0};
-    double cTw[4] = {0, 0, 0, 0};                   // absolute wall temperatures
+    int ckind[6] = {0, 0, 0, 0, 0, 0};
+    double cTw[6] = {0, 0, 0, 0, 0, 0};             // absolute wall temperatures
     std::vector<double> ccx, ccy, carea;            // host copy of the cell geometry
+    // 3D body-fitted mesh (rtlbfs_curv3_create)
+    bool curv3 = false;
+    Curv3Geo c3{};
+    const double *c3rec64[3] = {nullptr, nullptr, nullptr};  // FP64 face records (diagnostics)
+    std::vector<double> c3cx, c3cy, c3cz, c3vol;
 
     void *U(int k) { return ws + lay.off_U[k]; }
     double *parts() { return (double *)(ws + lay.off_parts); }
@@ -281,7 +287,22 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
 int curv_blocks(const rtlbfs_mesh &m) { return ((m.n[0] + kCTX - 1) / kCTX) * ((m.n[1] + kCTY - 1) / kCTY); }
 
 // Blocks of one step launch of the handle (rows of residual partials).
-int handle_blocks(const rtlbfs_t h, int tile) { return h->curv ? curv_blocks(h->mesh) : step_blocks(h->mesh, tile); }
+int handle_blocks(const rtlbfs_t h, int tile) {
+    if (h->curv3) return (int)((h->lay.cells + 255) / 256);
+    return h->curv ? curv_blocks(h->mesh) : step_blocks(h->mesh, tile);
+}
+
+template <typename R, bool DEV, bool TL>
+hipError_t launch_curv3(rtlbfs_t h, int src, bool res, hipStream_t s) {
+    const R *Uin = (const R *)h->U(src);
+    R *Uout = (R *)h->U(src ^ 1);
+    const int cb = (int)((h->lay.cells + 255) / 256), fb = (int)((h->c3.nfaces + 255) / 256);
+    k_c3_grad<R, DEV><<<cb, 256, 0, s>>>(h->dom, h->c3, Uin);
+    k_c3_flux<R, DEV, TL><<<fb, 256, 0, s>>>(h->dom, h->c3, Uin);
+    if (res) k_c3_update<R, DEV, true><<<cb, 256, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
+    else k_c3_update<R, DEV, false><<<cb, 256, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
+    return hipGetLastError();
+}
 
 template <typename R, bool DEV, bool TL>
 hipError_t launch_curv(rtlbfs_t h, int src, bool res, hipStream_t s) {
@@ -299,6 +320,16 @@ hipError_t launch_curv(rtlbfs_t h, int src, bool res, hipStream_t s) {
 // One step kernel from copy `src` into the other copy (no state change on the host side).
 hipError_t launch_any(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     const bool tl = h->opts.method == RTLBFS_METHOD_TLBFS;
+    if (h->curv3) {
+        switch (h->opts.precision) {
+            case RTLBFS_FP64_PLAIN:
+                return tl ? launch_curv3<double, false, true>(h, src, res, s) : launch_curv3<double, false, false>(h, src, res, s);
+            case RTLBFS_FP64_DEV:
+                return tl ? launch_curv3<double, true, true>(h, src, res, s) : launch_curv3<double, true, false>(h, src, res, s);
+            default:
+                return tl ? launch_curv3<float, true, true>(h, src, res, s) : launch_curv3<float, true, false>(h, src, res, s);
+        }
+    }
     if (h->curv) {
         switch (h->opts.precision) {
             case RTLBFS_FP64_PLAIN:
@@ -495,6 +526,60 @@ CurvLayout make_curv_layout(int ni, int nj, int precision) {
     m.n[1] = nj;
     m.n[2] = 1;
     l.nparts = std::max(kRedBlocks, curv_blocks(m));
+    l.off_parts = off;
+    off += align256(sizeof(double) * (size_t)l.nparts * 8);
+    l.off_red = off;
+    off += align256(sizeof(double) * 32);
+    l.bytes = off;
+    return l;
+}
+
+// Workspace of a 3D body-fitted mesh: two state copies, face records of the
+// three axes and 1/dV in the kernel precision (FP64 record copies only for
+// FP32), FP64 volumes, the per-step scratch (primitives, gradients, face
+// fluxes), partials and reduction slots.
+struct Curv3Layout {
+    size_t off_U[2], off_rec[3], off_rec64[3], off_iv, off_vol, off_prim, off_grad, off_flux, off_parts, off_red,
+        bytes;
+    int nparts;
+    int64_t nf[3];
+};
+
+Curv3Layout make_curv3_layout(const int n[3], int precision) {
+    Curv3Layout l{};
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const size_t es = elem_size(precision);
+    size_t off = 0;
+    for (int k = 0; k < 2; ++k) {
+        l.off_U[k] = off;
+        off += (size_t)5 * field_stride(cells) * es;
+    }
+    int64_t nfaces = 0;
+    for (int a = 0; a < 3; ++a) {
+        l.nf[a] = (int64_t)(n[0] + (a == 0)) * (n[1] + (a == 1)) * (n[2] + (a == 2));
+        nfaces += l.nf[a];
+        l.off_rec[a] = off;
+        off += align256((size_t)kC3Fields * l.nf[a] * es);
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (es == 4) {
+            l.off_rec64[a] = off;
+            off += align256((size_t)kC3Fields * l.nf[a] * sizeof(double));
+        } else {
+            l.off_rec64[a] = l.off_rec[a];
+        }
+    }
+    l.off_iv = off;
+    off += align256((size_t)cells * es);
+    l.off_vol = off;
+    off += align256((size_t)cells * sizeof(double));
+    l.off_prim = off;
+    off += align256((size_t)5 * cells * es);
+    l.off_grad = off;
+    off += align256((size_t)15 * cells * es);
+    l.off_flux = off;
+    off += align256((size_t)5 * nfaces * es);
+    l.nparts = std::max<int>(kRedBlocks, (int)((cells + 255) / 256));
     l.off_parts = off;
     off += align256(sizeof(double) * (size_t)l.nparts * 8);
     l.off_red = off;
@@ -729,7 +814,7 @@ int rtlbfs_residual(rtlbfs_t h, double *res_u, double *res_T) {
 
 int rtlbfs_nusselt(rtlbfs_t h, rtlbfs_nu *out) {
     if (!h || !out) return RTLBFS_EINVAL;
-    if (h->curv) return fail(h, RTLBFS_EUNSUPPORTED, "body-fitted mesh: use rtlbfs_wall_heat");
+    if (h->curv || h->curv3) return fail(h, RTLBFS_EUNSUPPORTED, "body-fitted mesh: use rtlbfs_wall_heat");
     const int ha = heat_axis(h->mesh, h->bc);
     if (ha < 0) return fail(h, RTLBFS_EINVAL, "no pair of isothermal walls");
     const double Tlo = h->bc.Tdev[2 * ha], Thi = h->bc.Tdev[2 * ha + 1];
@@ -836,7 +921,12 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
     for (int a = 0; a < 3; ++a) out->length[a] = a < h->mesh.dim ? h->length[a] : 1.0;
     out->precision = h->opts.precision;
     for (int t = 0; t < kNumTiles2; ++t) out->tune_ms[t] = h->tune_ms[t];
-    if (h->curv) {
+    if (h->curv3) {
+        out->tile_x = 256;  // one thread per cell or face, 256 per block
+        out->tile_y = 1;
+        out->tile_z = 1;
+        out->steps_per_launch = 1;
+    } else if (h->curv) {
         out->tile_x = kCTX;
         out->tile_y = kCTY;
         out->tile_z = 1;
@@ -1050,6 +1140,32 @@ int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, doub
 
 int rtlbfs_wall_heat(rtlbfs_t h, int side, double out[2]) {
     if (!h || !out) return RTLBFS_EINVAL;
+    if (h->curv3) {
+        if (side < 0 || side > 5 || h->ckind[side] != RTLBFS_WALL_ISOTHERMAL)
+            return fail(h, RTLBFS_EINVAL, "side is not an isothermal wall");
+        double *dst = h->red() + 5;
+        const int a = side / 2;
+        switch (h->opts.precision) {
+            case RTLBFS_FP64_PLAIN:
+                k_c3_wall_heat<double, false><<<1, 256, 0, h->stream>>>(h->dom, h->c3rec64[a], h->c3.sf[a],
+                                                                        (const double *)h->U(h->cur), side, h->cTw[side], dst);
+                break;
+            case RTLBFS_FP64_DEV:
+                k_c3_wall_heat<double, true><<<1, 256, 0, h->stream>>>(h->dom, h->c3rec64[a], h->c3.sf[a],
+                                                                       (const double *)h->U(h->cur), side, h->cTw[side], dst);
+                break;
+            default:
+                k_c3_wall_heat<float, true><<<1, 256, 0, h->stream>>>(h->dom, h->c3rec64[a], h->c3.sf[a],
+                                                                      (const float *)h->U(h->cur), side, h->cTw[side], dst);
+                break;
+        }
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(h->host_buf + 40, dst, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        out[0] = h->host_buf[40];
+        out[1] = h->host_buf[41];
+        return RTLBFS_OK;
+    }
     if (!h->curv) return fail(h, RTLBFS_EUNSUPPORTED, "rtlbfs_wall_heat needs a body-fitted mesh");
     if (side < 0 || side > 3 || h->ckind[side] != RTLBFS_WALL_ISOTHERMAL)
         return fail(h, RTLBFS_EINVAL, "side is not an isothermal wall");
@@ -1083,6 +1199,198 @@ int rtlbfs_curv_cells(rtlbfs_t h, double *cx, double *cy, double *area, size_t c
     if (cx) std::memcpy(cx, h->ccx.data(), h->ccx.size() * sizeof(double));
     if (cy) std::memcpy(cy, h->ccy.data(), h->ccy.size() * sizeof(double));
     if (area) std::memcpy(area, h->carea.data(), h->carea.size() * sizeof(double));
+    return RTLBFS_OK;
+}
+
+size_t rtlbfs_curv3_workspace_bytes(const rtlbfs_curv3_mesh *mesh, const rtlbfs_opts *opts) {
+    if (!mesh) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (mesh->n[a] < 1 || mesh->n[a] > (1 << 16)) return 0;
+    if ((int64_t)mesh->n[0] * mesh->n[1] * mesh->n[2] > (int64_t)1 << 28) return 0;
+    rtlbfs_opts o;
+    if (opts) o = *opts;
+    else rtlbfs_opts_init(&o);
+    return make_curv3_layout(mesh->n, o.precision).bytes;
+}
+
+int rtlbfs_curv3_create(const rtlbfs_curv3_mesh *mesh, double nu, double chi, double beta_g, const rtlbfs_curv3_bc *bc,
+                        const rtlbfs_opts *opts, void *hip_stream, void *workspace, size_t ws_bytes, rtlbfs_t *out) {
+    if (!out) return RTLBFS_EINVAL;
+    *out = nullptr;
+    g_create_err.clear();
+    rtlbfs_opts o;
+    if (opts) o = *opts;
+    else rtlbfs_opts_init(&o);
+    auto reject = [](const char *why) {
+        g_create_err = why;
+        return RTLBFS_EINVAL;
+    };
+    if (o.precision != RTLBFS_FP64_PLAIN && o.precision != RTLBFS_FP32_DEV && o.precision != RTLBFS_FP64_DEV)
+        return reject("unknown precision");
+    if (o.method != RTLBFS_METHOD_RTLBFS && o.method != RTLBFS_METHOD_TLBFS) return reject("unknown opts.method");
+    if (o.tile != 0) return reject("opts.tile must be 0 on a body-fitted mesh");
+    if (!(nu > 0.0) || !(chi > 0.0) || !(beta_g >= 0.0)) return reject("nu, chi > 0, beta_g >= 0");
+    if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return reject("dtl and dt must be >= 0");
+    if (!(o.max_mach >= 0.0) || o.max_mach > 10.0) return reject("opts.max_mach out of range");
+    Curv3Problem cp;
+    std::string why;
+    int rc = curv3_setup(mesh, bc, cp, why);
+    if (rc != RTLBFS_OK) {
+        g_create_err = why;
+        return rc;
+    }
+    Problem P;
+    P.mesh.dim = 3;
+    for (int a = 0; a < 3; ++a) P.mesh.n[a] = cp.n[a];
+    for (int s = 0; s < 6; ++s) {
+        P.bc.kind[s] = bc->kind[s];
+        P.bc.Tdev[s] = bc->Tw[s] - kT0;
+    }
+    P.bc.gravity_axis = -1;  // buoyancy along bc->up, applied by the body-fitted kernels
+    P.D = 3;
+    P.cells = cp.cells;
+    P.nu = nu;
+    P.chi = chi;
+    P.bg = beta_g;
+    P.dtl = o.dtl > 0.0 ? o.dtl : 1.0;
+    P.dt = o.dt > 0.0 ? o.dt : std::min(0.5, 0.15 / std::max(nu, chi));
+
+    rtlbfs_t h = new (std::nothrow) rtlbfs_handle();
+    if (!h) return RTLBFS_ENOMEM;
+    h->curv3 = true;
+    h->mesh = P.mesh;
+    h->bc = P.bc;
+    if (o.residual_every <= 0) o.residual_every = 100;
+    if (o.mass_fix_every == 0) o.mass_fix_every = 1000;
+    h->opts = o;
+    h->opts.dtl = P.dtl;
+    h->opts.dt = P.dt;
+    h->opts.nu = nu;
+    h->opts.chi = chi;
+    h->opts.beta_g = beta_g;
+    h->opts.phys_given = 1;
+    h->stream = (hipStream_t)hip_stream;
+    const Curv3Layout cl = make_curv3_layout(cp.n, o.precision);
+    h->lay = Layout{};
+    h->lay.off_U[0] = cl.off_U[0];
+    h->lay.off_U[1] = cl.off_U[1];
+    h->lay.off_parts = cl.off_parts;
+    h->lay.off_red = cl.off_red;
+    h->lay.bytes = cl.bytes;
+    h->lay.cells = cp.cells;
+    h->lay.nparts = cl.nparts;
+    h->L = 0.0;
+    for (int s = 0; s < 6; ++s) {
+        h->ckind[s] = bc->kind[s];
+        h->cTw[s] = bc->Tw[s];
+    }
+    h->c3cx = cp.cx;
+    h->c3cy = cp.cy;
+    h->c3cz = cp.cz;
+    h->c3vol = cp.vol;
+    Domain &d = h->dom;
+    fill_domain(P, o.precision, o.buoyancy_update_only ? 0 : 1, o.round_nearest, o.max_mach, d);
+    const bool dev = o.precision != RTLBFS_FP64_PLAIN;
+    d.phd.Tref_s = dev ? bc->T_ref - kT0 : bc->T_ref;
+    d.phf.Tref_s = (float)d.phd.Tref_s;
+    if (workspace) {
+        if (ws_bytes < cl.bytes) {
+            delete h;
+            g_create_err = "workspace smaller than rtlbfs_curv3_workspace_bytes()";
+            return RTLBFS_ENOMEM;
+        }
+        h->ws = (char *)workspace;
+    } else {
+        hipError_t e = hipMalloc((void **)&h->ws, cl.bytes);
+        if (e != hipSuccess) {
+            delete h;
+            g_create_err = "hipMalloc of the workspace failed";
+            return RTLBFS_ENOMEM;
+        }
+        h->own_ws = true;
+    }
+    {
+        const size_t es = elem_size(o.precision);
+        std::vector<double> iv(cp.cells);
+        for (int64_t c = 0; c < cp.cells; ++c) iv[c] = 1.0 / cp.vol[c];
+        hipError_t e = hipSuccess;
+        for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+            std::vector<char> b(cp.rec[a].size() * es);
+            if (es == 4) put<float>(b.data(), cp.rec[a]);
+            else put<double>(b.data(), cp.rec[a]);
+            e = hipMemcpy(h->ws + cl.off_rec[a], b.data(), b.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess && es == 4)
+                e = hipMemcpy(h->ws + cl.off_rec64[a], cp.rec[a].data(), cp.rec[a].size() * sizeof(double),
+                              hipMemcpyHostToDevice);
+        }
+        std::vector<char> biv(iv.size() * es);
+        if (es == 4) put<float>(biv.data(), iv);
+        else put<double>(biv.data(), iv);
+        if (e == hipSuccess) e = hipMemcpy(h->ws + cl.off_iv, biv.data(), biv.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(h->ws + cl.off_vol, cp.vol.data(), cp.vol.size() * sizeof(double), hipMemcpyHostToDevice);
+        const uint32_t zero2[2] = {0u, 0u};
+        if (e == hipSuccess) e = hipMemcpy(h->ctr(), zero2, sizeof(zero2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&h->host_buf, 64 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            int r2 = hip_fail(h, e, "upload geometry / capture stream");
+            g_create_err = h->err;
+            rtlbfs_destroy(h);
+            return r2;
+        }
+    }
+    d.vol = (const double *)(h->ws + cl.off_vol);
+    for (int a = 0; a < 3; ++a) {
+        d.w[a] = nullptr;
+        d.geo[a] = nullptr;
+    }
+    Curv3Geo &g = h->c3;
+    for (int a = 0; a < 3; ++a) {
+        g.f[a] = h->ws + cl.off_rec[a];
+        g.sf[a] = cl.nf[a];
+        h->c3rec64[a] = (const double *)(h->ws + cl.off_rec64[a]);
+        g.rc[a] = std::cos(bc->rot[a]);
+        g.rs[a] = std::sin(bc->rot[a]);
+        g.up[a] = bc->up[a];
+        g.upf[a] = (float)bc->up[a];
+    }
+    g.nfaces = cl.nf[0] + cl.nf[1] + cl.nf[2];
+    g.inv_vol = h->ws + cl.off_iv;
+    g.prim = h->ws + cl.off_prim;
+    g.grad = h->ws + cl.off_grad;
+    g.flux = h->ws + cl.off_flux;
+
+    const int64_t N = cp.cells;
+    std::vector<double> rho((size_t)N, 1.0), u((size_t)N * 3, 0.0), T((size_t)N);
+    for (int64_t c = 0; c < N; ++c) T[c] = bc->T_ref - kT0 + o.noise_amp * splitmix_uniform(o.seed, (uint64_t)c);
+    rc = upload_prims(h, rho.data(), u.data(), T.data());
+    if (rc == RTLBFS_OK) {
+        hipError_t e = enqueue_integrals(h, h->int_out(), h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->m0(), h->int_out(), sizeof(double), hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = hip_fail(h, e, "initial integrals");
+    }
+    if (rc != RTLBFS_OK) {
+        g_create_err = h->err;
+        rtlbfs_destroy(h);
+        return rc;
+    }
+    h->tile = 0;
+    *out = h;
+    return RTLBFS_OK;
+}
+
+int rtlbfs_curv3_cells(rtlbfs_t h, double *cx, double *cy, double *cz, double *vol, size_t count) {
+    if (!h) return RTLBFS_EINVAL;
+    if (!h->curv3) return fail(h, RTLBFS_EUNSUPPORTED, "not a 3D body-fitted mesh");
+    if (count < h->c3cx.size()) return fail(h, RTLBFS_EINVAL, "count smaller than the cell count");
+    const size_t b = h->c3cx.size() * sizeof(double);
+    if (cx) std::memcpy(cx, h->c3cx.data(), b);
+    if (cy) std::memcpy(cy, h->c3cy.data(), b);
+    if (cz) std::memcpy(cz, h->c3cz.data(), b);
+    if (vol) std::memcpy(vol, h->c3vol.data(), b);
     return RTLBFS_OK;
 }
 

@@ -62,6 +62,16 @@ class CurvBC(C.Structure):
                 ("u_inf", C.c_double * 2), ("T_inf", C.c_double)]
 
 
+class Curv3Mesh(C.Structure):
+    _fields_ = [("n", C.c_int * 3), ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
+                ("z", C.POINTER(C.c_double))]
+
+
+class Curv3BC(C.Structure):
+    _fields_ = [("kind", C.c_int * 6), ("rot", C.c_double * 3), ("Tw", C.c_double * 6), ("up", C.c_double * 3),
+                ("T_ref", C.c_double)]
+
+
 class NuOut(C.Structure):
     _fields_ = [("hot_avg", C.c_double), ("hot_max", C.c_double), ("cold_avg", C.c_double),
                 ("cold_max", C.c_double), ("volume", C.c_double)]
@@ -137,6 +147,11 @@ def load_library() -> C.CDLL:
                                        C.POINTER(VP)]
     lib.rtlbfs_wall_heat.argtypes = [VP, I, PD]
     lib.rtlbfs_curv_cells.argtypes = [VP, PD, PD, PD, SZ]
+    lib.rtlbfs_curv3_workspace_bytes.argtypes = [C.POINTER(Curv3Mesh), C.POINTER(Opts)]
+    lib.rtlbfs_curv3_workspace_bytes.restype = SZ
+    lib.rtlbfs_curv3_create.argtypes = [C.POINTER(Curv3Mesh), D, D, D, C.POINTER(Curv3BC), C.POINTER(Opts), VP, VP,
+                                        SZ, C.POINTER(VP)]
+    lib.rtlbfs_curv3_cells.argtypes = [VP, PD, PD, PD, PD, SZ]
     lib.rtlbfs_batch_workspace_bytes.argtypes = [I, C.POINTER(Mesh), C.POINTER(Opts)]
     lib.rtlbfs_batch_workspace_bytes.restype = SZ
     lib.rtlbfs_batch_create.argtypes = [I, C.POINTER(Mesh), PD, PD, D, C.POINTER(BC), C.POINTER(Opts), VP, VP, SZ,
@@ -152,7 +167,8 @@ def load_library() -> C.CDLL:
     for name in ("rtlbfs_opts_init", "rtlbfs_mesh_nodes", "rtlbfs_create", "rtlbfs_step", "rtlbfs_sync",
                  "rtlbfs_residual", "rtlbfs_nusselt", "rtlbfs_integrals", "rtlbfs_get_field", "rtlbfs_get_stored",
                  "rtlbfs_set_state", "rtlbfs_get_info", "rtlbfs_destroy", "rtlbfs_curv_create", "rtlbfs_wall_heat",
-                 "rtlbfs_curv_cells", "rtlbfs_batch_create", "rtlbfs_batch_step",
+                 "rtlbfs_curv_cells", "rtlbfs_curv3_create", "rtlbfs_curv3_cells", "rtlbfs_batch_create",
+                 "rtlbfs_batch_step",
                  "rtlbfs_batch_nusselt", "rtlbfs_batch_residual", "rtlbfs_batch_get_field", "rtlbfs_batch_get_info",
                  "rtlbfs_batch_sync", "rtlbfs_batch_diverged", "rtlbfs_batch_destroy"):
         getattr(lib, name).restype = I
@@ -375,6 +391,63 @@ class CurvSolver(Solver):
         cx, cy, a = np.zeros(self.cells), np.zeros(self.cells), np.zeros(self.cells)
         self._check(self._lib.rtlbfs_curv_cells(self._h, _pd(cx), _pd(cy), _pd(a), self.cells), "rtlbfs_curv_cells")
         return cx, cy, a
+
+
+class Curv3Solver(Solver):
+    """One 3D body-fitted (structured curvilinear) hexahedral mesh advanced by
+    the gfx950 kernels: vertex arrays x, y, z of shape (nk + 1, nj + 1, ni + 1),
+    sides (i-, i+, j-, j+, k-, k+) PERIODIC / WALL_ISOTHERMAL / WALL_ADIABATIC,
+    `rot` closing periodic axes by a rotation about z, absolute temperatures,
+    buoyancy beta_g (T - T_ref) along the unit vector `up`; starts at rest at
+    T = T_ref."""
+
+    def __init__(self, x, y, z, kind: Sequence[int], rot: Sequence[float] = (0.0, 0.0, 0.0),
+                 Tw: Sequence[float] = (0.0,) * 6, up: Sequence[float] = (0.0, 0.0, 0.0), T_ref: float = 0.5,
+                 nu: float = 0.1, chi: float = 0.1, beta_g: float = 0.0, **opts):
+        self._h = None
+        self._lib = load_library()
+        x, y, z = (np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, z))
+        if x.ndim != 3 or not (x.shape == y.shape == z.shape):
+            raise ValueError("x, y, z must be (nk + 1, nj + 1, ni + 1) arrays")
+        self.dim = 3
+        self.cmesh = Curv3Mesh()
+        self.cmesh.n[:] = [x.shape[2] - 1, x.shape[1] - 1, x.shape[0] - 1]
+        self.cmesh.x, self.cmesh.y, self.cmesh.z = _pd(x), _pd(y), _pd(z)
+        self._xyz = (x, y, z)
+        self.cbc = Curv3BC()
+        self.cbc.kind[:] = [int(v) for v in kind]
+        self.cbc.rot[:] = [float(v) for v in rot]
+        self.cbc.Tw[:] = [float(v) for v in Tw]
+        self.cbc.up[:] = [float(v) for v in up]
+        self.cbc.T_ref = float(T_ref)
+        self.opts = make_opts(**opts)
+        nbytes = self._lib.rtlbfs_curv3_workspace_bytes(C.byref(self.cmesh), C.byref(self.opts))
+        if nbytes == 0:
+            raise RtlbfsError(EINVAL, "invalid mesh")
+        self.workspace, self.stream = _torch_stream_and_alloc(nbytes)
+        h = C.c_void_p()
+        rc = self._lib.rtlbfs_curv3_create(C.byref(self.cmesh), nu, chi, beta_g, C.byref(self.cbc),
+                                           C.byref(self.opts), C.c_void_p(self.stream),
+                                           C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), C.byref(h))
+        if rc != OK:
+            detail = self._lib.rtlbfs_last_error(None).decode()
+            raise RtlbfsError(rc, f"rtlbfs_curv3_create: {strerror(rc)}: {detail}")
+        self._h = h
+        self.info = self.get_info()
+        self.cells = int(self.info.cells)
+        self.shape = tuple(int(v) for v in self.cmesh.n)
+
+    def wall_heat(self, side: int) -> tuple[float, float]:
+        """(sum (T_w - T_P)/d dS, sum dS) over the faces of an isothermal side."""
+        out = np.zeros(2)
+        self._check(self._lib.rtlbfs_wall_heat(self._h, side, _pd(out)), "rtlbfs_wall_heat")
+        return float(out[0]), float(out[1])
+
+    def geometry(self):
+        """Cell centroids (x, y, z) and volumes the library derived."""
+        out = [np.zeros(self.cells) for _ in range(4)]
+        self._check(self._lib.rtlbfs_curv3_cells(self._h, *(_pd(v) for v in out), self.cells), "rtlbfs_curv3_cells")
+        return tuple(out)
 
 
 class Batch:

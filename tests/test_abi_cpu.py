@@ -233,3 +233,49 @@ def test_curv_workspace_bytes_and_cartesian_only_calls():
     out = np.zeros(2)
     assert lib.rtlbfs_wall_heat(None, 2, rtb._pd(out)) == rt.EINVAL
     assert lib.rtlbfs_curv_cells(None, None, None, None, 0) == rt.EINVAL
+
+
+def _c3_create(X, Y, Z, bc, nu=0.1, opts=None):
+    lib = rt.load_library()
+    m = rtb.Curv3Mesh()
+    m.n[:] = [X.shape[2] - 1, X.shape[1] - 1, X.shape[0] - 1]
+    X, Y, Z = (np.ascontiguousarray(v) for v in (X, Y, Z))
+    m.x, m.y, m.z = rtb._pd(X), rtb._pd(Y), rtb._pd(Z)
+    o = opts or rt.make_opts()
+    h = C.c_void_p()
+    rc = lib.rtlbfs_curv3_create(C.byref(m), nu, 0.1, 0.0, C.byref(bc), C.byref(o), None, None, 0, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["farfield", "pair", "rot_walled", "not_closed", "folded", "up", "tile", "nu",
+                                  "small"])
+def test_curv3_create_rejects_invalid_problems_before_touching_the_device(case):
+    import inputs
+    X, Y, Z = inputs.annulus_wedge(5, 1, 4, 10.0, 15.0, 4.0, 0.1)
+    b = rtb.Curv3BC()
+    b.kind[:] = [1, 1, 0, 0, 2, 2]
+    b.rot[:] = [0.0, 0.1, 0.0]
+    b.up[:] = [0.0, 0.0, 1.0]
+    kw = {}
+    if case == "farfield":
+        b.kind[1] = 3
+    elif case == "pair":
+        b.kind[3] = 2
+    elif case == "rot_walled":
+        b.rot[0] = 0.1
+    elif case == "not_closed":
+        b.rot[1] = 0.12
+    elif case == "folded":
+        X, Y, Z = X.copy(), Y.copy(), Z.copy()
+        X[:, :, 2], X[:, :, 3] = X[:, :, 3].copy(), X[:, :, 2].copy()
+        Y[:, :, 2], Y[:, :, 3] = Y[:, :, 3].copy(), Y[:, :, 2].copy()
+    elif case == "up":
+        b.up[:] = [0.0, 0.5, 0.5]
+    elif case == "tile":
+        kw["opts"] = rt.make_opts(tile=2)
+    elif case == "nu":
+        kw["nu"] = -1.0
+    elif case == "small":
+        X, Y, Z = X[:, :, :2], Y[:, :, :2], Z[:, :, :2]  # one radial cell between two walls
+    rc, h = _c3_create(X, Y, Z, b, **kw)
+    assert rc == rt.EINVAL and not h.value, rt.load_library().rtlbfs_last_error(None)
