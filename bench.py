@@ -649,6 +649,73 @@ def cylinder_table4_bench(rt, torch, steps, warmup, chunk=200_000, max_steps=4_0
     return {"workload": "cylinder Table 4 (Re=20, Pr=0.7, Gr 0/100/800/1600), FP32 deviation", "rows": rows}
 
 
+TABLE7 = {1e4: (3.212, 3.222), 1e5: (5.791, 5.810)}
+
+
+def annulus_solver(rt, Ra, precision, **opts):
+    """The Sec. 4.5 wedge (120 x 1 x 240, rotation-closed, wedge angle 1/R_i),
+    Pr = 0.71, V_c = 0.1 (Eq. 77: beta g = V_c^2 / (dT (R_o - R_i)))."""
+    import math
+
+    from paper_2202_13449_amd.workloads import annulus_mesh
+
+    x, y, z, Ri, Ro, H, dth = annulus_mesh()
+    L, Vc, Pr = Ro - Ri, 0.1, 0.71
+    nu = Vc * L * math.sqrt(Pr / Ra)
+    s = rt.Curv3Solver(np.array(x), np.array(y), np.array(z), (rt.WALL_ISOTHERMAL, rt.WALL_ISOTHERMAL, rt.PERIODIC,
+                       rt.PERIODIC, rt.WALL_ADIABATIC, rt.WALL_ADIABATIC), rot=(0.0, dth, 0.0),
+                       Tw=(1.0, 0.0, 0, 0, 0, 0), up=(0.0, 0.0, 1.0), T_ref=0.5, nu=nu, chi=nu / Pr,
+                       beta_g=Vc * Vc / L, precision=precision, noise_amp=1e-6, seed=1, **opts)
+    return s, Ri, Ro
+
+
+def annulus_bench(rt, torch, steps, warmup):
+    """Time per step of the three body-fitted 3D kernels on the Sec. 4.5
+    wedge (28,800 cells), Ra = 1e5, FP32 deviation and FP64 plain, residual
+    once per KERNEL_CHUNK steps."""
+    out = {"workload": "annulus 120x1x240 wedge Ra=1e5 (Sec. 4.5)", "cells": 120 * 240}
+    for name, prec in (("fp32_dev", rt.FP32_DEV), ("fp64_plain", rt.FP64_PLAIN)):
+        s, _, _ = annulus_solver(rt, 1e5, prec, residual_every=KERNEL_CHUNK, mass_fix_every=-1)
+        s.step(max(warmup, KERNEL_CHUNK))
+        s.sync()
+        ms = timed(torch, s, max(KERNEL_CHUNK, steps - steps % KERNEL_CHUNK))
+        out[name] = {"ms_per_step": ms, "value": s.cells / (ms * 1e-3)}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
+def annulus_table7_bench(rt, torch, steps, warmup, chunk=100_000, max_steps=1_500_000):
+    """Sec. 4.5, Table 7: the 120 x 1 x 240 annulus wedge (one azimuthal cell,
+    rotation-closed, wedge angle 1/R_i), Pr = 0.71, V_c = 0.1 (Eq. 77),
+    FP32 deviation storage, from rest until the inner Nusselt number moves by
+    less than 1e-6 relative over `chunk` steps; Eq. 78 on both cylinders as
+    R (T_w - T_P)/d averaged over the wall.  Also the time per step of the
+    three body-fitted 3D kernels."""
+    rows = {}
+    for Ra, (ni_ref, no_ref) in TABLE7.items():
+        s, Ri, Ro = annulus_solver(rt, Ra, rt.FP32_DEV, residual_every=1000)
+        done, prev = 0, None
+        t0 = time.perf_counter()
+        while done < max_steps:
+            s.step(chunk)
+            done += chunk
+            qi, Ai = s.wall_heat(0)
+            qo, Ao = s.wall_heat(1)
+            nui, nuo = Ri * qi / Ai, -Ro * qo / Ao
+            if prev is not None and abs(nui - prev) < 1e-6 * nui:
+                break
+            prev = nui
+        ms = timed(torch, s, max(steps, 1000))
+        rows[f"{Ra:.0e}"] = {"Nu_i": nui, "Nu_i_paper": ni_ref, "Nu_o": nuo, "Nu_o_paper": no_ref,
+                             "Nu_i_rel_err": abs(nui - ni_ref) / ni_ref, "Nu_o_rel_err": abs(nuo - no_ref) / no_ref,
+                             "steps": done, "residual": s.residual(), "seconds": time.perf_counter() - t0,
+                             "ms_per_step": ms, "cell_updates_per_s": s.cells / (ms * 1e-3)}
+        del s
+        torch.cuda.empty_cache()
+    return {"workload": "annulus Table 7 (Ar=2, eta=2, Pr=0.71, 120x1x240 wedge), FP32 deviation", "rows": rows}
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle, as written, on a bounded sample of the same workload."""
     from oracle import Oracle, OracleConfig, physics_from_ra, mesh_nodes
@@ -683,13 +750,15 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
     ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods",
-                                                           "stability", "cylinder", "cylinder_table4"],
+                                                           "stability", "cylinder", "cylinder_table4", "annulus", "annulus_table7"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
                          "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
                          "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5; "
                          "hill: the Gaussian-hill convergence study of Sec. 4.1; methods: RTLBFS vs TLBFS step cost; "
                          "stability: the stability maps of Figs. 4-5 as batched runs; cylinder: the body-fitted "
-                         "step on the 450x300 O-mesh of Sec. 4.3; cylinder_table4: Table 4, Gr 0..1600")
+                         "step on the 450x300 O-mesh of Sec. 4.3; cylinder_table4: Table 4, Gr 0..1600; "
+                         "annulus: the body-fitted 3D step on the 120x1x240 wedge of Sec. 4.5; "
+                         "annulus_table7: that annulus against Table 7")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     args = ap.parse_args()
@@ -720,7 +789,8 @@ def main():
         fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,
               "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench,
               "stability": stability_bench, "cylinder": cylinder_bench,
-              "cylinder_table4": cylinder_table4_bench}[args.workload]
+              "cylinder_table4": cylinder_table4_bench, "annulus": annulus_bench,
+              "annulus_table7": annulus_table7_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE

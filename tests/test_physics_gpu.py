@@ -220,3 +220,43 @@ def test_heated_cylinder_matches_table4(Gr):
     assert abs(Nu - nu_ref) <= 0.005 * nu_ref, (Nu, nu_ref)
     assert abs(sep - sep_ref) <= 0.6, (sep, sep_ref)
     assert max(s.residual()) < 1e-6
+
+
+def _table7():
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table7_annulus.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            ra, ni, no = (float(t) for t in line.split())
+            rows[ra] = (ni, no)
+    return rows
+
+
+@pytest.mark.parametrize("Ra", [1e4, 1e5])
+def test_annulus_matches_table7(Ra):
+    """Sec. 4.5: the 120 x 1 x 240 wedge of the concentric annulus (one
+    azimuthal cell closed by a rotation about z, wedge angle 1/R_i), FP32
+    deviation storage, 500,000 steps from rest (steady after about 400,000
+    at Ra = 1e5).  Eq. 78 on both cylinders within 0.2% of the printed
+    'Present' values: R (T_w - T_P)/d averaged over the wall, with V_c from
+    Eq. 77 and T_ref = 0.5."""
+    import math
+
+    from paper_2202_13449_amd.workloads import annulus_mesh
+
+    ni_ref, no_ref = _table7()[Ra]
+    x, y, z, Ri, Ro, H, dth = annulus_mesh()
+    L, Vc, Pr = Ro - Ri, 0.1, 0.71
+    nu = Vc * L * math.sqrt(Pr / Ra)
+    s = rt.Curv3Solver(np.array(x), np.array(y), np.array(z), (rt.WALL_ISOTHERMAL, rt.WALL_ISOTHERMAL, rt.PERIODIC,
+                       rt.PERIODIC, rt.WALL_ADIABATIC, rt.WALL_ADIABATIC), rot=(0.0, dth, 0.0),
+                       Tw=(1.0, 0.0, 0, 0, 0, 0), up=(0.0, 0.0, 1.0), T_ref=0.5, nu=nu, chi=nu / Pr,
+                       beta_g=Vc * Vc / L, precision=rt.FP32_DEV, residual_every=1000, noise_amp=1e-6, seed=1)
+    s.step(500_000)
+    qi, Ai = s.wall_heat(0)
+    qo, Ao = s.wall_heat(1)
+    Nu_i, Nu_o = Ri * qi / Ai, -Ro * qo / Ao
+    assert abs(Nu_i - ni_ref) <= 0.002 * ni_ref, (Nu_i, ni_ref)
+    assert abs(Nu_o - no_ref) <= 0.002 * no_ref, (Nu_o, no_ref)
+    assert max(s.residual()) < 1e-6
