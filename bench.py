@@ -50,8 +50,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step2d_fp32_cavity256.j
 
 def kernel_sources_sha256() -> str:
     """Hash of what defines the 2D step kernel (its device headers, its
-    __global__ wrapper and the build flags), so stored counter data is used
-    only while that kernel is unchanged."""
+    __global__ wrapper and the compile flags of build.py), so stored counter
+    data is used only while that kernel is unchanged."""
     import hashlib
     import re
 
@@ -65,8 +65,12 @@ def kernel_sources_sha256() -> str:
     if not m:
         raise RuntimeError("k_step2d wrapper not found in rtlbfs_api.hip")
     h.update(b"k_step2d\0" + m.group(0).encode())
-    with open(os.path.join(ROOT, "paper_2202_13449_amd", "build.py"), "rb") as f:
-        h.update(b"build.py\0" + f.read())
+    with open(os.path.join(ROOT, "paper_2202_13449_amd", "build.py")) as f:
+        build = f.read()
+    fm = re.search(r"flags = \[.*?\]", build, re.S)  # the code-generation flags, not the file lists
+    if not fm:
+        raise RuntimeError("compile flags not found in build.py")
+    h.update(b"build flags\0" + fm.group(0).encode())
     return h.hexdigest()
 
 
