@@ -270,8 +270,10 @@ size_t rtlbfs_curv_workspace_bytes(const rtlbfs_curv_mesh *mesh, const rtlbfs_op
  * (opts->phys_given and Ra/Pr/Ma do not apply).  The state starts at rho = 1,
  * u = u_inf, T = T_inf (+ opts->noise_amp noise on T).  Every other option,
  * the workspace and stream rules and the error codes are those of
- * rtlbfs_create; opts->tile must be 0 (one 16 x 16 launch shape) and
- * opts->init is ignored.  The handle works with rtlbfs_step, _sync,
+ * rtlbfs_create, except: opts->tile 0 autotunes the launch shape among
+ * 16 x 16, 16 x 8, 32 x 8 and 8 x 8 cells (every shape timed on the live
+ * state at create), 1..4 fixes one of them in that order; opts->init is
+ * ignored.  The handle works with rtlbfs_step, _sync,
  * _residual, _integrals, _get_field, _set_state, _get_stored, _get_info and
  * _destroy; rtlbfs_nusselt returns RTLBFS_EUNSUPPORTED (use
  * rtlbfs_wall_heat).  EINVAL also for a mesh that folds over or does not

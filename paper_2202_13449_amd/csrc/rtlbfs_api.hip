@@ -54,20 +54,28 @@ __global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
-constexpr int kCTX = 16, kCTY = 16;  // tile of the body-fitted step kernel
+// Launch shapes of the body-fitted 2D step kernel (opts.tile = index + 1);
+// the autotuner picks one per handle (the best shape depends on the mesh and
+// the precision: 16 x 8 and 8 x 8 spread a 450 x 300 mesh over the CUs more
+// evenly than 16 x 16).
+struct TileC {
+    int tx, ty;
+};
+constexpr TileC kTilesC[] = {{16, 16}, {16, 8}, {32, 8}, {8, 8}};
+constexpr int kNumTilesC = sizeof(kTilesC) / sizeof(kTilesC[0]);
 
-template <typename R, bool DEV, bool TL, bool RES>
-__global__ void __launch_bounds__((curv_threads<kCTX, kCTY>())) k_curv_step(Domain d, CurvGeo g,
-                                                                          const R *__restrict__ Uin,
-                                                                          R *__restrict__ Uout,
-                                                                          double *__restrict__ parts,
-                                                                          const uint32_t *__restrict__ ctr_in,
-                                                                          uint32_t *__restrict__ ctr_out) {
+template <typename R, bool DEV, bool TL, int TX, int TY, bool RES>
+__global__ void __launch_bounds__((curv_threads<TX, TY>())) k_curv_step(Domain d, CurvGeo g,
+                                                                      const R *__restrict__ Uin,
+                                                                      R *__restrict__ Uout,
+                                                                      double *__restrict__ parts,
+                                                                      const uint32_t *__restrict__ ctr_in,
+                                                                      uint32_t *__restrict__ ctr_out) {
     const uint32_t key = *ctr_in;
-    const int ntx = (d.n[0] + kCTX - 1) / kCTX;
+    const int ntx = (d.n[0] + TX - 1) / TX;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    tile_step_curv<R, DEV, TL, kCTX, kCTY, RES>(d, g, (t % ntx) * kCTX, (t / ntx) * kCTY, Uin, Uout,
-                                                parts + (int64_t)t * kPartials, key);
+    tile_step_curv<R, DEV, TL, TX, TY, RES>(d, g, (t % ntx) * TX, (t / ntx) * TY, Uin, Uout,
+                                            parts + (int64_t)t * kPartials, key);
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
 }
 
@@ -284,12 +292,15 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     return hipGetLastError();
 }
 
-int curv_blocks(const rtlbfs_mesh &m) { return ((m.n[0] + kCTX - 1) / kCTX) * ((m.n[1] + kCTY - 1) / kCTY); }
+int curv_blocks(const rtlbfs_mesh &m, int tile) {
+    const TileC t = kTilesC[tile];
+    return ((m.n[0] + t.tx - 1) / t.tx) * ((m.n[1] + t.ty - 1) / t.ty);
+}
 
 // Blocks of one step launch of the handle (rows of residual partials).
 int handle_blocks(const rtlbfs_t h, int tile) {
     if (h->curv3) return (int)((h->lay.cells + 255) / 256);
-    return h->curv ? curv_blocks(h->mesh) : step_blocks(h->mesh, tile);
+    return h->curv ? curv_blocks(h->mesh, tile) : step_blocks(h->mesh, tile);
 }
 
 template <typename R, bool DEV, bool TL>
@@ -304,17 +315,27 @@ hipError_t launch_curv3(rtlbfs_t h, int src, bool res, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename R, bool DEV, bool TL>
-hipError_t launch_curv(rtlbfs_t h, int src, bool res, hipStream_t s) {
+template <typename R, bool DEV, bool TL, int TX, int TY>
+hipError_t launch_curv_shape(rtlbfs_t h, int src, bool res, hipStream_t s) {
     const R *Uin = (const R *)h->U(src);
     R *Uout = (R *)h->U(src ^ 1);
     const uint32_t *ci = h->ctr() + src;
     uint32_t *co = h->ctr() + (src ^ 1);
-    const int nb = curv_blocks(h->mesh);
-    constexpr int nt = curv_threads<kCTX, kCTY>();
-    if (res) k_curv_step<R, DEV, TL, true><<<nb, nt, 0, s>>>(h->dom, h->cg, Uin, Uout, h->parts(), ci, co);
-    else k_curv_step<R, DEV, TL, false><<<nb, nt, 0, s>>>(h->dom, h->cg, Uin, Uout, h->parts(), ci, co);
+    const int nb = ((h->mesh.n[0] + TX - 1) / TX) * ((h->mesh.n[1] + TY - 1) / TY);
+    constexpr int nt = curv_threads<TX, TY>();
+    if (res) k_curv_step<R, DEV, TL, TX, TY, true><<<nb, nt, 0, s>>>(h->dom, h->cg, Uin, Uout, h->parts(), ci, co);
+    else k_curv_step<R, DEV, TL, TX, TY, false><<<nb, nt, 0, s>>>(h->dom, h->cg, Uin, Uout, h->parts(), ci, co);
     return hipGetLastError();
+}
+
+template <typename R, bool DEV, bool TL>
+hipError_t launch_curv(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
+    switch (tile) {
+        case 0: return launch_curv_shape<R, DEV, TL, 16, 16>(h, src, res, s);
+        case 1: return launch_curv_shape<R, DEV, TL, 16, 8>(h, src, res, s);
+        case 2: return launch_curv_shape<R, DEV, TL, 32, 8>(h, src, res, s);
+        default: return launch_curv_shape<R, DEV, TL, 8, 8>(h, src, res, s);
+    }
 }
 
 // One step kernel from copy `src` into the other copy (no state change on the host side).
@@ -333,11 +354,14 @@ hipError_t launch_any(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
     if (h->curv) {
         switch (h->opts.precision) {
             case RTLBFS_FP64_PLAIN:
-                return tl ? launch_curv<double, false, true>(h, src, res, s) : launch_curv<double, false, false>(h, src, res, s);
+                return tl ? launch_curv<double, false, true>(h, tile, src, res, s)
+                          : launch_curv<double, false, false>(h, tile, src, res, s);
             case RTLBFS_FP64_DEV:
-                return tl ? launch_curv<double, true, true>(h, src, res, s) : launch_curv<double, true, false>(h, src, res, s);
+                return tl ? launch_curv<double, true, true>(h, tile, src, res, s)
+                          : launch_curv<double, true, false>(h, tile, src, res, s);
             default:
-                return tl ? launch_curv<float, true, true>(h, src, res, s) : launch_curv<float, true, false>(h, src, res, s);
+                return tl ? launch_curv<float, true, true>(h, tile, src, res, s)
+                          : launch_curv<float, true, false>(h, tile, src, res, s);
         }
     }
     switch (h->opts.precision) {
@@ -413,8 +437,10 @@ hipError_t enqueue_mass_fix(rtlbfs_t h, hipStream_t s) {
 // and the tiles are timed in interleaved rounds, keeping each tile's best
 // round, so that clock ramps and neighbours on the device bias no tile.
 int autotune_tile(rtlbfs_t h) {
-    if (h->mesh.dim != 2) return RTLBFS_OK;
+    if (h->mesh.dim != 2 || h->curv3) return RTLBFS_OK;
     constexpr int kLaunches = 32, kRounds = 4;
+    const int nshapes = h->curv ? kNumTilesC : kNumTiles2;
+    auto nsub = [&](int t) { return h->curv ? 1 : kTiles2[t].nsub; };
     hipGraphExec_t ge[kNumTiles2] = {};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = RTLBFS_OK;
@@ -428,7 +454,7 @@ int autotune_tile(rtlbfs_t h) {
     };
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    for (int t = 0; t < kNumTiles2 && e == hipSuccess; ++t) {
+    for (int t = 0; t < nshapes && e == hipSuccess; ++t) {
         hipGraph_t g = nullptr;
         e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) break;
@@ -439,23 +465,23 @@ int autotune_tile(rtlbfs_t h) {
         if (e == hipSuccess) e = hipGraphInstantiate(&ge[t], g, nullptr, nullptr, 0);
         if (g) (void)hipGraphDestroy(g);
     }
-    for (int t = 0; t < kNumTiles2 && e == hipSuccess; ++t) e = hipGraphLaunch(ge[t], h->stream);  // warm-up
+    for (int t = 0; t < nshapes && e == hipSuccess; ++t) e = hipGraphLaunch(ge[t], h->stream);  // warm-up
     for (int r = 0; r < kRounds && e == hipSuccess; ++r) {
-        for (int t = 0; t < kNumTiles2 && e == hipSuccess; ++t) {
+        for (int t = 0; t < nshapes && e == hipSuccess; ++t) {
             e = hipEventRecord(e0, h->stream);
             if (e == hipSuccess) e = hipGraphLaunch(ge[t], h->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess) best_ms[t] = std::min(best_ms[t], ms / (kLaunches * kTiles2[t].nsub));
+            if (e == hipSuccess) best_ms[t] = std::min(best_ms[t], ms / (kLaunches * nsub(t)));
         }
     }
     if (e != hipSuccess) rc = hip_fail(h, e, "tile autotuning");
     cleanup();
     if (rc != RTLBFS_OK) return rc;
     int best_t = 0;
-    for (int t = 0; t < kNumTiles2; ++t) {
+    for (int t = 0; t < nshapes; ++t) {
         h->tune_ms[t] = best_ms[t];
         if (best_ms[t] < best_ms[best_t]) best_t = t;
     }
@@ -525,7 +551,8 @@ CurvLayout make_curv_layout(int ni, int nj, int precision) {
     m.n[0] = ni;
     m.n[1] = nj;
     m.n[2] = 1;
-    l.nparts = std::max(kRedBlocks, curv_blocks(m));
+    l.nparts = kRedBlocks;
+    for (int t = 0; t < kNumTilesC; ++t) l.nparts = std::max(l.nparts, curv_blocks(m, t));
     l.off_parts = off;
     off += align256(sizeof(double) * (size_t)l.nparts * 8);
     l.off_red = off;
@@ -927,8 +954,8 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
         out->tile_z = 1;
         out->steps_per_launch = 1;
     } else if (h->curv) {
-        out->tile_x = kCTX;
-        out->tile_y = kCTY;
+        out->tile_x = kTilesC[h->tile].tx;
+        out->tile_y = kTilesC[h->tile].ty;
         out->tile_z = 1;
         out->steps_per_launch = 1;
     } else if (h->mesh.dim == 2) {
@@ -968,7 +995,7 @@ int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, doub
     if (o.precision != RTLBFS_FP64_PLAIN && o.precision != RTLBFS_FP32_DEV && o.precision != RTLBFS_FP64_DEV)
         return reject("unknown precision");
     if (o.method != RTLBFS_METHOD_RTLBFS && o.method != RTLBFS_METHOD_TLBFS) return reject("unknown opts.method");
-    if (o.tile != 0) return reject("opts.tile must be 0 on a body-fitted mesh");
+    if (o.tile < 0 || o.tile > kNumTilesC) return reject("opts.tile out of range for a body-fitted 2D mesh (0..4)");
     if (!(nu > 0.0) || !(chi > 0.0) || !(beta_g >= 0.0)) return reject("nu, chi > 0, beta_g >= 0");
     if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return reject("dtl and dt must be >= 0");
     if (!(o.max_mach >= 0.0) || o.max_mach > 10.0) return reject("opts.max_mach out of range");
@@ -1128,12 +1155,15 @@ int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, doub
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) rc = hip_fail(h, e, "initial integrals");
     }
+    if (rc == RTLBFS_OK) {
+        if (o.tile > 0) h->tile = o.tile - 1;
+        else rc = autotune_tile(h);
+    }
     if (rc != RTLBFS_OK) {
         g_create_err = h->err;
         rtlbfs_destroy(h);
         return rc;
     }
-    h->tile = 0;
     *out = h;
     return RTLBFS_OK;
 }

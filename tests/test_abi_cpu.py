@@ -202,7 +202,7 @@ def test_curv_create_rejects_invalid_problems_before_touching_the_device(case):
     elif case == "up":
         bc.up[:] = [0.5, 0.5]
     elif case == "tile":
-        kw["opts"] = rt.make_opts(tile=1)
+        kw["opts"] = rt.make_opts(tile=5)
     elif case == "nu":
         kw["nu"] = 0.0
     elif case == "beta_g":
