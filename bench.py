@@ -605,6 +605,7 @@ def cylinder_bench(rt, torch, steps, warmup):
         tf = FLOPS_PER_CELL_CURV[key] * cells / (ms * 1e-3) / 1e12
         peak = FP32_VECTOR_PEAK_TFLOPS if key == "f32" else FP64_VECTOR_PEAK_TFLOPS
         out[name] = {"ms_per_step": ms, "value": cells / (ms * 1e-3), "kernel_us": ms * 1e3, "tflops": tf,
+                     "tile": [s.info.tile_x, s.info.tile_y],
                      "frac": tf / peak, "peak": peak, "flops_per_cell": FLOPS_PER_CELL_CURV[key],
                      "bytes_per_cell": BYTES_PER_CELL_CURV[key],
                      "hbm_gbs": BYTES_PER_CELL_CURV[key] * cells / (ms * 1e-3) / 1e9}
