@@ -155,7 +155,10 @@ __global__ void __launch_bounds__(256) k_c3_grad(Domain d, Curv3Geo g, const R *
     R acc[5][3];
 #pragma unroll
     for (int p = 0; p < 5; ++p) acc[p][0] = acc[p][1] = acc[p][2] = (R)0;
+    // unrolled, so the loads of all six faces and neighbours are in flight together
+#pragma unroll
     for (int a = 0; a < 3; ++a)
+#pragma unroll
         for (int hi = 0; hi < 2; ++hi) {
             int fq[3] = {i, j, k};
             fq[a] += hi;
@@ -335,6 +338,7 @@ __global__ void __launch_bounds__(256) k_c3_update(Domain d, Curv3Geo g, const R
         const R *fl = (const R *)g.flux;
         R div[5] = {0, 0, 0, 0, 0};
         int64_t base = 0;
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
             int hq[3] = {i, j, k};
             hq[a] += 1;
