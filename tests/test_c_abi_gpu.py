@@ -1,8 +1,10 @@
 """The C ABI used from plain C: tests/abi_c/abi_check (built by build() with
 gcc against include/rtlbfs.h and librtlbfs.so) runs a cavity with a
-library-owned workspace on the null stream and a two-member batch, in a
-process without torch or Python.  Its state must equal the binding's run of
-the same problem bit for bit."""
+library-owned workspace on the null stream, a two-member batch, a 2D
+body-fitted O-mesh annulus (heated wall, far field, buoyancy) and a 3D
+annulus wedge closed by a rotation, in a process without torch or Python.
+Its results must equal the binding's runs of the same problems bit for bit
+(the meshes are read back from the files the program wrote)."""
 import json
 import os
 import subprocess
@@ -38,3 +40,21 @@ def test_plain_c_program_matches_the_binding(tmp_path):
     assert res["bad_field_rc"] == rt.EINVAL
     assert res["batch_diverged"] == [0, 0]
     assert res["batch_nu_hot0"] > 1.0
+    assert res["curv_nusselt_rc"] == rt.EUNSUPPORTED
+
+    base = out_T
+    ni, nj = 36, 14
+    cx = np.fromfile(base + ".cx").reshape(nj + 1, ni + 1)
+    cy = np.fromfile(base + ".cy").reshape(nj + 1, ni + 1)
+    c = rt.CurvSolver(cx, cy, (rt.PERIODIC, rt.PERIODIC, rt.WALL_ISOTHERMAL, rt.FARFIELD), Tw=(0, 0, 1.0, 0),
+                      up=(0.0, 1.0), T_ref=0.0, u_inf=(0.0, 0.04), T_inf=0.0, nu=0.08, chi=0.11, beta_g=4e-5, dt=0.5)
+    c.step(steps)
+    assert list(c.wall_heat(2)) == res["curv_wall_heat"]
+
+    nr, nz = 8, 10
+    x3, y3, z3 = (np.fromfile(base + e).reshape(nz + 1, 2, nr + 1) for e in (".c3x", ".c3y", ".c3z"))
+    w = rt.Curv3Solver(x3, y3, z3, (rt.WALL_ISOTHERMAL, rt.WALL_ISOTHERMAL, rt.PERIODIC, rt.PERIODIC,
+                                    rt.WALL_ADIABATIC, rt.WALL_ADIABATIC), rot=(0.0, 0.1, 0.0),
+                       Tw=(1.0, 0, 0, 0, 0, 0), up=(0.0, 0.0, 1.0), T_ref=0.5, nu=0.06, chi=0.08, beta_g=5e-4, dt=0.5)
+    w.step(steps)
+    assert list(w.wall_heat(0)) == res["curv3_wall_heat"]
