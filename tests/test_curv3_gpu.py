@@ -131,3 +131,19 @@ def test_annulus_wedge_fp32_deviation():
     o.step(300)
     rel = rel_errors(s, o)
     assert max(rel[1:]) <= 1e-5 and rel[0] <= 1e-4, rel
+
+
+def test_graph_replay_equals_eager_launches_3d():
+    X, Y, Z = wedge()
+    bc = wedge_bc(1)
+    kw = dict(rot=bc["rot"], Tw=bc["Tw"], up=bc["up"], T_ref=0.5, nu=0.06, chi=0.08, beta_g=bc["beta_g"],
+              precision=rt.FP32_DEV, dt=0.5, residual_every=40)
+    a = rt.Curv3Solver(X, Y, Z, bc["kind"], **kw)
+    b = rt.Curv3Solver(X, Y, Z, bc["kind"], graph_steps=-1, **kw)
+    for s in (a, b):
+        s.step(250)
+    for f in range(5):
+        assert np.array_equal(a.stored(f), b.stored(f)), f
+    with pytest.raises(rt.RtlbfsError) as e:
+        a.wall_heat(4)  # adiabatic
+    assert e.value.code == rt.EINVAL

@@ -168,3 +168,45 @@ def test_launch_shapes_give_identical_fields(precision):
         fields.append(np.vstack([s.stored(f) for f in range(4)]))
     for k in range(1, 5):
         assert np.array_equal(fields[k], fields[0]), k
+
+
+def test_graph_replay_equals_eager_launches_and_errors_are_reported():
+    """Body-fitted handles step through the same graph-replayed chunks as the
+    Cartesian ones; eager launches (graph_steps < 0) give the same bits.
+    Misuse returns the documented codes."""
+    x, y = annulus()
+    kw = dict(Tw=CYL["Tw"], up=CYL["up"], T_ref=0.0, u_inf=CYL["u_inf"], T_inf=0.0, nu=0.08, chi=0.11,
+              beta_g=CYL["beta_g"], precision=rt.FP32_DEV, dt=0.5, residual_every=40)
+    a = rt.CurvSolver(x, y, CYL["kind"], **kw)
+    b = rt.CurvSolver(x, y, CYL["kind"], graph_steps=-1, **kw)
+    for s in (a, b):
+        s.step(250)
+    for f in range(4):
+        assert np.array_equal(a.stored(f), b.stored(f)), f
+    assert a.residual() == b.residual()
+    with pytest.raises(rt.RtlbfsError) as e:
+        a.wall_heat(3)  # the far-field side is not an isothermal wall
+    assert e.value.code == rt.EINVAL
+    with pytest.raises(rt.RtlbfsError) as e:
+        a.nusselt()
+    assert e.value.code == rt.EUNSUPPORTED
+
+
+def test_fp32_mass_fix_uses_the_cell_areas():
+    """Closed annulus (adiabatic walls on both radial sides), FP32 deviation
+    storage: with the total-mass correction every 50 steps the FP64 sum of
+    r dV stays at its initial value; the correction subtracts one uniform
+    shift weighted by the body-fitted cell areas."""
+    x, y = annulus(ni=40, nj=21, r_in=30.0, r_out=120.0, first=2.0)
+    kind = (PER, PER, ADI, ADI)
+    s = rt.CurvSolver(x, y, kind, up=(0.0, 1.0), T_ref=0.5, T_inf=0.5, nu=0.08, chi=0.11, beta_g=2e-4,
+                      precision=rt.FP32_DEV, dt=0.5, mass_fix_every=50)
+    rho, u, T = inputs.random_state(s.cells, 2, seed=101)
+    s.set_state(rho, u, T)
+    m0 = s.integrals()["mass_dev"]
+    s.step(2000)
+    m1 = s.integrals()["mass_dev"]
+    vol = s.integrals()["volume"]
+    _, _, area = s.geometry()
+    assert abs(vol - area.sum()) <= 1e-12 * vol
+    assert abs(m1 - m0) <= 1e-9 * vol, (m0, m1)
