@@ -21,13 +21,15 @@
 //      into LDS (new conserved state and primitives) for an intermediate
 //      sub-step; to HBM, with the FP64 partial sums of Eq. 65 on residual
 //      steps, for the last one.
-// The block has one thread per face of the largest update region (rounded up
-// to whole wavefronts), so every phase is a single straight pass.  Latency,
-// not issue rate, decides the time of a small domain (one tile per CU), so
-// the phases avoid divergence: all interior faces, x and y alike, run one
-// code path with per-lane LDS addresses, and neighbour values are read
-// unconditionally and chosen by selects rather than by branches around
-// single LDS reads.
+// The block has one thread per face of the largest update region, the x-faces
+// and the y-faces each rounded up to whole wavefronts, so every phase is a
+// single straight pass.  A wavefront holds faces of one axis only: the axis is
+// wave-uniform, its branch is a scalar one, and each side runs code
+// specialised for its axis (compile-time field and gradient offsets, no
+// per-lane selects between x and y).  Within a wavefront the phases avoid
+// divergence: interior faces run one code path, and neighbour values are read
+// unconditionally and chosen by selects rather than by branches around single
+// LDS reads.
 #pragma once
 
 #include "rtlbfs_device.h"
@@ -40,10 +42,22 @@ constexpr int region_faces() {
     return (UX + 1) * UY + UX * (UY + 1);
 }
 
+// Threads of a UX x UY update region's face pass: the x-faces in whole
+// wavefronts, then the y-faces in whole wavefronts.
+template <int UX, int UY>
+constexpr int region_face_threads() {
+    return ((UX + 1) * UY + 63) / 64 * 64 + (UX * (UY + 1) + 63) / 64 * 64;
+}
+
 template <int TX, int TY, int NSUB = 1>
 constexpr int tile2_threads() {
-    return (region_faces<TX + 4 * (NSUB - 1), TY + 4 * (NSUB - 1)>() + 63) / 64 * 64;
+    return region_face_threads<TX + 4 * (NSUB - 1), TY + 4 * (NSUB - 1)>();
 }
+
+template <int V>
+struct AxisTag {
+    static constexpr int value = V;
+};
 
 // Block -> tile order that keeps each XCD on a contiguous band of tiles.
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
@@ -85,8 +99,10 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
     constexpr int GX = UX + 2, GY = UY + 2;  // gradients with a 1-cell halo
     constexpr int NFX = (UX + 1) * UY;
     constexpr int NF = region_faces<UX, UY>();
+    constexpr int WX = (NFX + 63) / 64 * 64;  // threads of the x-faces: whole wavefronts
     constexpr int PF = PX * PY, GF = GX * GY;  // field strides in sp and sg
-    static_assert(GX * GY <= NT && NF <= NT && UX * UY <= NT, "every phase is one pass of the block");
+    static_assert(GX * GY <= NT && region_face_threads<UX, UY>() <= NT && UX * UY <= NT,
+                  "every phase is one pass of the block");
     const int nx = d.n[0], ny = d.n[1];
     const int64_t N = d.fstride;
     const bool px = d.periodic[0], py = d.periodic[1];
@@ -146,65 +162,71 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
     // (b) every face once.  x-face (lx, ly): between cells (lx - 1, ly) and
     // (lx, ly) of the region; y-face (lx, ly): between (lx, ly - 1) and
     // (lx, ly).  On a periodic axis every face is real (the halo wraps); on a
-    // walled axis the faces run from the low wall to the high wall.
-    if (tid < NF) {
-        const bool isx = tid < NFX;
-        const int qy = tid - NFX;
-        const int lx = isx ? tid % (UX + 1) : qy % UX;
-        const int ly = isx ? tid / (UX + 1) : qy / UX;
+    // walled axis the faces run from the low wall to the high wall.  Threads
+    // [0, WX) take the x-faces, [WX, WX + NF - NFX) the y-faces; the fluxes
+    // go to sf with the x-faces first.
+    auto face = [&](auto tag, int q) {
+        constexpr bool isx = decltype(tag)::value == 0;
+        constexpr int FW = isx ? UX + 1 : UX;  // faces per row
+        constexpr int NFA = isx ? NFX : NF - NFX;
+        if (q >= NFA) return;
+        const int lx = q % FW, ly = q / FW;
         const int gx = ux0 + lx, gy = uy0 + ly;
         const bool okx = px || (isx ? (gx >= 0 && gx <= nx) : (gx >= 0 && gx < nx));
         const bool oky = py || (isx ? (gy >= 0 && gy < ny) : (gy >= 0 && gy <= ny));
-        if (okx && oky) {
-            const int ax = isx ? 1 : 0, ay = isx ? 0 : 1;  // step from the low to the high cell
-            const int hx = lx + 2, hy = ly + 2;               // high cell in sp
-            const int lox = hx - ax, loy = hy - ay;           // low cell in sp
-            const int gface = isx ? gx : gy, nn = isx ? nx : ny;
-            const bool wall = !(isx ? px : py) && (gface == 0 || gface == nn);
-            const R area = isx ? GEOY(kGeoW, hy) : GEOX(kGeoW, hx);
-            // components in the face frame: (r, u_n, u_t, T); y-faces swap u, v
-            const int pn = isx ? 1 : 2, pt = isx ? 2 : 1;
-            R G[4];
-            if (wall) {
-                const bool low = gface == 0;  // wall on the low side: the fluid cell is the high one
-                const int side = isx ? (low ? 0 : 1) : (low ? 2 : 3);
-                const int wx = low ? hx : lox, wy = low ? hy : loy;
-                const R sgn = low ? (R)-1 : (R)1;
-                const R rP = SP(0, wy, wx);
-                const R rho = DEV ? (R)1 + rP : rP;
-                const R wcell = isx ? GEOX(kGeoW, wx) : GEOY(kGeoW, wy);
-                const R d_w = (R)0.5 * wcell;
-                const R mloc[2] = {rho * SP(pn, wy, wx), rho * SP(pt, wy, wx)};
-                wall_flux<R, 2, DEV>(rP, mloc, rho * SP(3, wy, wx), sgn, d_w, swIso[side] != 0, swT[side], ph, G);
-            } else {
-                Side<R, 2> A, B;
-                const int gn = isx ? 0 : 1, gt = isx ? 1 : 0;  // gradient components along n and t
-                const int pp[4] = {0, pn, pt, 3};
-                const int gL = (loy - 1) * GX + (lox - 1), gR = (hy - 1) * GX + (hx - 1);
+        if (!(okx && oky)) return;
+        constexpr int ax = isx ? 1 : 0, ay = isx ? 0 : 1;  // step from the low to the high cell
+        const int hx = lx + 2, hy = ly + 2;                 // high cell in sp
+        const int lox = hx - ax, loy = hy - ay;             // low cell in sp
+        const int gface = isx ? gx : gy, nn = isx ? nx : ny;
+        const bool wall = !(isx ? px : py) && (gface == 0 || gface == nn);
+        const R area = isx ? GEOY(kGeoW, hy) : GEOX(kGeoW, hx);
+        // components in the face frame: (r, u_n, u_t, T); y-faces swap u, v
+        constexpr int pn = isx ? 1 : 2, pt = isx ? 2 : 1;
+        R G[4];
+        if (wall) {
+            const bool low = gface == 0;  // wall on the low side: the fluid cell is the high one
+            const int side = isx ? (low ? 0 : 1) : (low ? 2 : 3);
+            const int wx = low ? hx : lox, wy = low ? hy : loy;
+            const R sgn = low ? (R)-1 : (R)1;
+            const R rP = SP(0, wy, wx);
+            const R rho = DEV ? (R)1 + rP : rP;
+            const R wcell = isx ? GEOX(kGeoW, wx) : GEOY(kGeoW, wy);
+            const R d_w = (R)0.5 * wcell;
+            const R mloc[2] = {rho * SP(pn, wy, wx), rho * SP(pt, wy, wx)};
+            wall_flux<R, 2, DEV>(rP, mloc, rho * SP(3, wy, wx), sgn, d_w, swIso[side] != 0, swT[side], ph, G);
+        } else {
+            Side<R, 2> A, B;
+            constexpr int gn = isx ? 0 : 1, gt = isx ? 1 : 0;  // gradient components along n and t
+            constexpr int pp[4] = {0, pn, pt, 3};
+            const int gL = (loy - 1) * GX + (lox - 1), gR = (hy - 1) * GX + (hx - 1);
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    A.v[p] = SP(pp[p], loy, lox);
-                    B.v[p] = SP(pp[p], hy, hx);
-                    A.g[0][p] = v.sg[(pp[p] * 2 + gn) * GF + gL];
-                    A.g[1][p] = v.sg[(pp[p] * 2 + gt) * GF + gL];
-                    B.g[0][p] = v.sg[(pp[p] * 2 + gn) * GF + gR];
-                    B.g[1][p] = v.sg[(pp[p] * 2 + gt) * GF + gR];
-                }
-                const R wL = isx ? GEOX(kGeoW, lox) : GEOY(kGeoW, loy);
-                const R wR = isx ? GEOX(kGeoW, hx) : GEOY(kGeoW, hy);
-                const int na = isx ? 0 : 1, ta = isx ? 1 : 0;
-                const R fdir[2] = {(d.force_pred && d.gaxis == na) ? (R)1 : (R)0,
-                                   (d.force_pred && d.gaxis == ta) ? (R)1 : (R)0};
-                if constexpr (TL) face_flux_tlbfs<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
-                else face_flux<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
+            for (int p = 0; p < 4; ++p) {
+                A.v[p] = SP(pp[p], loy, lox);
+                B.v[p] = SP(pp[p], hy, hx);
+                A.g[0][p] = v.sg[(pp[p] * 2 + gn) * GF + gL];
+                A.g[1][p] = v.sg[(pp[p] * 2 + gt) * GF + gL];
+                B.g[0][p] = v.sg[(pp[p] * 2 + gn) * GF + gR];
+                B.g[1][p] = v.sg[(pp[p] * 2 + gt) * GF + gR];
             }
-            // back to global components (mass, m_x, m_y, energy)
-            v.sf[0 * NF + tid] = G[0] * area;
-            v.sf[1 * NF + tid] = (isx ? G[1] : G[2]) * area;
-            v.sf[2 * NF + tid] = (isx ? G[2] : G[1]) * area;
-            v.sf[3 * NF + tid] = G[3] * area;
+            const R wL = isx ? GEOX(kGeoW, lox) : GEOY(kGeoW, loy);
+            const R wR = isx ? GEOX(kGeoW, hx) : GEOY(kGeoW, hy);
+            constexpr int na = isx ? 0 : 1, ta = isx ? 1 : 0;
+            const R fdir[2] = {(d.force_pred && d.gaxis == na) ? (R)1 : (R)0,
+                               (d.force_pred && d.gaxis == ta) ? (R)1 : (R)0};
+            if constexpr (TL) face_flux_tlbfs<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
+            else face_flux<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
         }
-    }
+        // back to global components (mass, m_x, m_y, energy)
+        const int fo = isx ? q : NFX + q;
+        v.sf[0 * NF + fo] = G[0] * area;
+        v.sf[1 * NF + fo] = (isx ? G[1] : G[2]) * area;
+        v.sf[2 * NF + fo] = (isx ? G[2] : G[1]) * area;
+        v.sf[3 * NF + fo] = G[3] * area;
+    };
+    // the wavefront index, read as a scalar: the axis branch is uniform
+    if (__builtin_amdgcn_readfirstlane(tid >> 6) < WX / 64) face(AxisTag<0>{}, tid);
+    else face(AxisTag<1>{}, tid - WX);
     __syncthreads();
 
     // (c) divergence, Boussinesq source and update.  The last sub-step updates
