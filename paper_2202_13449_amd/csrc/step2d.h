@@ -21,13 +21,19 @@
 //      into LDS (new conserved state and primitives) for an intermediate
 //      sub-step; to HBM, with the FP64 partial sums of Eq. 65 on residual
 //      steps, for the last one.
-// The block has one thread per face of the largest update region, the x-faces
-// and the y-faces each rounded up to whole wavefronts, so every phase is a
-// single straight pass.  A wavefront holds faces of one axis only: the axis is
-// wave-uniform, its branch is a scalar one, and each side runs code
-// specialised for its axis (compile-time field and gradient offsets, no
-// per-lane selects between x and y).  Within a wavefront the phases avoid
-// divergence: interior faces run one code path, and neighbour values are read
+// The block has one thread per face of the largest update region, so every
+// phase is a single straight pass.  The face pass comes in two layouts:
+//   - shared (one-step launches): x- and y-faces side by side, rounded up to
+//     whole wavefronts once; all interior faces run one code path with the
+//     face frame chosen per lane (LDS addresses and selects);
+//   - split (two-step launches): the x-faces and the y-faces each in whole
+//     wavefronts, so the axis is wave-uniform and each side runs code with its
+//     frame fixed (compile-time offsets, no per-lane selects between x and y).
+// The split costs idle lanes where a face count is not a multiple of 64 and
+// pays where one tile per CU makes the per-lane instruction count the step's
+// time; a two-step launch is chosen for exactly such small domains, and for
+// its 20 x 20 first region (420 + 420 faces) the split adds no wavefront.
+// Within a wavefront the phases avoid divergence: neighbour values are read
 // unconditionally and chosen by selects rather than by branches around single
 // LDS reads.
 #pragma once
@@ -42,22 +48,25 @@ constexpr int region_faces() {
     return (UX + 1) * UY + UX * (UY + 1);
 }
 
-// Threads of a UX x UY update region's face pass: the x-faces in whole
-// wavefronts, then the y-faces in whole wavefronts.
-template <int UX, int UY>
+// Threads of a UX x UY update region's face pass: all faces in whole
+// wavefronts (shared layout), or the x-faces and then the y-faces each in
+// whole wavefronts (split layout).
+template <int UX, int UY, bool SPLIT>
 constexpr int region_face_threads() {
-    return ((UX + 1) * UY + 63) / 64 * 64 + (UX * (UY + 1) + 63) / 64 * 64;
+    return SPLIT ? ((UX + 1) * UY + 63) / 64 * 64 + (UX * (UY + 1) + 63) / 64 * 64
+                 : (region_faces<UX, UY>() + 63) / 64 * 64;
+}
+
+// The face pass of a two-step launch uses the split layout.
+template <int NSUB>
+constexpr bool split_faces() {
+    return NSUB == 2;
 }
 
 template <int TX, int TY, int NSUB = 1>
 constexpr int tile2_threads() {
-    return region_face_threads<TX + 4 * (NSUB - 1), TY + 4 * (NSUB - 1)>();
+    return region_face_threads<TX + 4 * (NSUB - 1), TY + 4 * (NSUB - 1), split_faces<NSUB>()>();
 }
-
-template <int V>
-struct AxisTag {
-    static constexpr int value = V;
-};
 
 // Block -> tile order that keeps each XCD on a contiguous band of tiles.
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
@@ -91,7 +100,7 @@ struct SubView {
     int gsx, gsy, gx0, gy0;
 };
 
-template <typename R, bool DEV, bool TL, int UX, int UY, bool LAST, bool RES, int NT>
+template <typename R, bool DEV, bool TL, int UX, int UY, bool LAST, bool RES, int NT, bool SPLIT>
 __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, const SubView<R> &v, R *sp_next,
                                            const R *swT, const int *swIso, R *__restrict__ Uout,
                                            double *__restrict__ part, double *sred, uint32_t step_key) {
@@ -99,9 +108,9 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
     constexpr int GX = UX + 2, GY = UY + 2;  // gradients with a 1-cell halo
     constexpr int NFX = (UX + 1) * UY;
     constexpr int NF = region_faces<UX, UY>();
-    constexpr int WX = (NFX + 63) / 64 * 64;  // threads of the x-faces: whole wavefronts
+    constexpr int WX = (NFX + 63) / 64 * 64;  // split layout: threads of the x-faces
     constexpr int PF = PX * PY, GF = GX * GY;  // field strides in sp and sg
-    static_assert(GX * GY <= NT && region_face_threads<UX, UY>() <= NT && UX * UY <= NT,
+    static_assert(GX * GY <= NT && region_face_threads<UX, UY, SPLIT>() <= NT && UX * UY <= NT,
                   "every phase is one pass of the block");
     const int nx = d.n[0], ny = d.n[1];
     const int64_t N = d.fstride;
@@ -162,27 +171,27 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
     // (b) every face once.  x-face (lx, ly): between cells (lx - 1, ly) and
     // (lx, ly) of the region; y-face (lx, ly): between (lx, ly - 1) and
     // (lx, ly).  On a periodic axis every face is real (the halo wraps); on a
-    // walled axis the faces run from the low wall to the high wall.  Threads
-    // [0, WX) take the x-faces, [WX, WX + NF - NFX) the y-faces; the fluxes
-    // go to sf with the x-faces first.
-    auto face = [&](auto tag, int q) {
-        constexpr bool isx = decltype(tag)::value == 0;
-        constexpr int FW = isx ? UX + 1 : UX;  // faces per row
-        constexpr int NFA = isx ? NFX : NF - NFX;
+    // walled axis the faces run from the low wall to the high wall.  The
+    // fluxes go to sf with the x-faces first.  face(isx, q) handles face q of
+    // its axis; it is inlined at each call, so a literal isx folds every
+    // choice between x and y.
+    auto face = [&](bool isx, int q) __attribute__((always_inline)) {
+        const int FW = isx ? UX + 1 : UX;  // faces per row
+        const int NFA = isx ? NFX : NF - NFX;
         if (q >= NFA) return;
         const int lx = q % FW, ly = q / FW;
         const int gx = ux0 + lx, gy = uy0 + ly;
         const bool okx = px || (isx ? (gx >= 0 && gx <= nx) : (gx >= 0 && gx < nx));
         const bool oky = py || (isx ? (gy >= 0 && gy < ny) : (gy >= 0 && gy <= ny));
         if (!(okx && oky)) return;
-        constexpr int ax = isx ? 1 : 0, ay = isx ? 0 : 1;  // step from the low to the high cell
+        const int ax = isx ? 1 : 0, ay = isx ? 0 : 1;  // step from the low to the high cell
         const int hx = lx + 2, hy = ly + 2;                 // high cell in sp
         const int lox = hx - ax, loy = hy - ay;             // low cell in sp
         const int gface = isx ? gx : gy, nn = isx ? nx : ny;
         const bool wall = !(isx ? px : py) && (gface == 0 || gface == nn);
         const R area = isx ? GEOY(kGeoW, hy) : GEOX(kGeoW, hx);
         // components in the face frame: (r, u_n, u_t, T); y-faces swap u, v
-        constexpr int pn = isx ? 1 : 2, pt = isx ? 2 : 1;
+        const int pn = isx ? 1 : 2, pt = isx ? 2 : 1;
         R G[4];
         if (wall) {
             const bool low = gface == 0;  // wall on the low side: the fluid cell is the high one
@@ -197,8 +206,8 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
             wall_flux<R, 2, DEV>(rP, mloc, rho * SP(3, wy, wx), sgn, d_w, swIso[side] != 0, swT[side], ph, G);
         } else {
             Side<R, 2> A, B;
-            constexpr int gn = isx ? 0 : 1, gt = isx ? 1 : 0;  // gradient components along n and t
-            constexpr int pp[4] = {0, pn, pt, 3};
+            const int gn = isx ? 0 : 1, gt = isx ? 1 : 0;  // gradient components along n and t
+            const int pp[4] = {0, pn, pt, 3};
             const int gL = (loy - 1) * GX + (lox - 1), gR = (hy - 1) * GX + (hx - 1);
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
@@ -211,7 +220,7 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
             }
             const R wL = isx ? GEOX(kGeoW, lox) : GEOY(kGeoW, loy);
             const R wR = isx ? GEOX(kGeoW, hx) : GEOY(kGeoW, hy);
-            constexpr int na = isx ? 0 : 1, ta = isx ? 1 : 0;
+            const int na = isx ? 0 : 1, ta = isx ? 1 : 0;
             const R fdir[2] = {(d.force_pred && d.gaxis == na) ? (R)1 : (R)0,
                                (d.force_pred && d.gaxis == ta) ? (R)1 : (R)0};
             if constexpr (TL) face_flux_tlbfs<R, 2, DEV>(A, B, (R)0.5 * wL, (R)0.5 * wR, fdir, ph, G);
@@ -224,9 +233,15 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
         v.sf[2 * NF + fo] = (isx ? G[2] : G[1]) * area;
         v.sf[3 * NF + fo] = G[3] * area;
     };
-    // the wavefront index, read as a scalar: the axis branch is uniform
-    if (__builtin_amdgcn_readfirstlane(tid >> 6) < WX / 64) face(AxisTag<0>{}, tid);
-    else face(AxisTag<1>{}, tid - WX);
+    if constexpr (SPLIT) {
+        // threads [0, WX) take the x-faces, [WX, WX + NF - NFX) the y-faces;
+        // the wavefront index, read as a scalar, makes the branch uniform
+        if (__builtin_amdgcn_readfirstlane(tid >> 6) < WX / 64) face(true, tid);
+        else face(false, tid - WX);
+    } else {
+        // threads [0, NFX) take the x-faces, [NFX, NF) the y-faces
+        if (tid < NF) face(tid < NFX, tid < NFX ? tid : tid - NFX);
+    }
     __syncthreads();
 
     // (c) divergence, Boussinesq source and update.  The last sub-step updates
@@ -407,20 +422,21 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     }
     __syncthreads();
 
+    constexpr bool SPL = split_faces<NSUB>();
     if constexpr (NSUB == 1) {
         const SubView<R> v{spA, sg, sf, sc, 0, TX, SCF, sgx, sgy, LX, LY, 0, 0};
-        substep_2d<R, DEV, TL, TX, TY, true, RES, NT>(d, i0, j0, v, nullptr, swT, swIso, Uout, part, sred,
-                                                      step_key);
+        substep_2d<R, DEV, TL, TX, TY, true, RES, NT, SPL>(d, i0, j0, v, nullptr, swT, swIso, Uout, part, sred,
+                                                           step_key);
     } else {
         const SubView<R> va{spA, sg, sf, sc, 0, U0X, SCF, sgx, sgy, LX, LY, 0, 0};
-        substep_2d<R, DEV, TL, U0X, U0Y, false, false, NT>(d, i0 - 2, j0 - 2, va, spB, swT, swIso, nullptr,
-                                                           nullptr, sred, step_key);
+        substep_2d<R, DEV, TL, U0X, U0Y, false, false, NT, SPL>(d, i0 - 2, j0 - 2, va, spB, swT, swIso, nullptr,
+                                                                nullptr, sred, step_key);
         __syncthreads();
         // second sub-step: primitives from spB, old state inside sc at (2, 2),
         // geometry shifted by the two cells the region shrank by
         const SubView<R> vb{spB, sg, sf, sc, 2 * U0X + 2, U0X, SCF, sgx, sgy, LX, LY, 2, 2};
-        substep_2d<R, DEV, TL, TX, TY, true, RES, NT>(d, i0, j0, vb, nullptr, swT, swIso, Uout, part, sred,
-                                                      step_key + 1u);
+        substep_2d<R, DEV, TL, TX, TY, true, RES, NT, SPL>(d, i0, j0, vb, nullptr, swT, swIso, Uout, part, sred,
+                                                           step_key + 1u);
     }
 }
 
