@@ -53,6 +53,19 @@ struct Curv3Geo {
     float upf[3];
 };
 
+// Element a of a 3-array (6-array) held in the kernel arguments, chosen by
+// selects: indexing such an array, or a private one, with a run-time index
+// would copy it to scratch memory and read it back with a dependent load.
+template <typename T>
+__device__ inline T pick3(int a, const T (&v)[3]) {
+    return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
+}
+
+template <typename T>
+__device__ inline T pick6(int s, const T (&v)[6]) {
+    return s < 3 ? (s == 0 ? v[0] : (s == 1 ? v[1] : v[2])) : (s == 3 ? v[3] : (s == 4 ? v[4] : v[5]));
+}
+
 template <typename R>
 __device__ inline R c3_up(const Curv3Geo &g, int a) {
     if constexpr (sizeof(R) == 4) return g.upf[a];
@@ -146,9 +159,10 @@ __device__ inline void c3_prims(const Domain &d, const R *__restrict__ U, int64_
 
 template <typename R, bool DEV>
 __global__ void __launch_bounds__(256) k_c3_grad(Domain d, Curv3Geo g, const R *__restrict__ U) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= d.cells) return;
-    const int i = (int)(c % d.n[0]), j = (int)((c / d.n[0]) % d.n[1]), k = (int)(c / ((int64_t)d.n[0] * d.n[1]));
+    // 32-bit index arithmetic: a body-fitted mesh holds at most 2^28 cells
+    const int c = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+    if (c >= (int)d.cells) return;
+    const int i = c % d.n[0], jk = c / d.n[0], j = jk % d.n[1], k = jk / d.n[1];
     const int q[3] = {i, j, k};
     R P[5];
     c3_prims<R, DEV>(d, U, c, P);
@@ -169,23 +183,26 @@ __global__ void __launch_bounds__(256) k_c3_grad(Domain d, Curv3Geo g, const R *
             const R sz = so * rec[kC3Nz * st] * rec[kC3DS * st];
             double cr, sr;
             const int64_t nb = c3_neighbour(d, g, q, a, hi, cr, sr);
+            // The neighbour is read unconditionally (a wall face reads the
+            // cell itself and discards it), so the loads of all six faces are
+            // issued together instead of one wall branch after another.
+            const bool wall = nb < 0;
+            R Q[5];
+            c3_prims<R, DEV>(d, U, wall ? (int64_t)c : nb, Q);
+            R u[3] = {Q[1], Q[2], Q[3]};
+            rot_z<R>((R)cr, (R)sr, u);
+            Q[1] = u[0];
+            Q[2] = u[1];
+            Q[3] = u[2];
+            const R wL = rec[kC3WL * st];
+            const int side = 2 * a + hi;
+            const R Tw = d.kind[side] == kIsothermal ? wall_T<R>(d, side) : P[4];
+            const R pw[5] = {P[0], (R)0, (R)0, (R)0, Tw};  // wall values
             R phi[5];
-            if (nb < 0) {
-                const int side = 2 * a + hi;
-                phi[0] = P[0];
-                phi[1] = phi[2] = phi[3] = (R)0;
-                phi[4] = d.kind[side] == kIsothermal ? wall_T<R>(d, side) : P[4];
-            } else {
-                R Q[5];
-                c3_prims<R, DEV>(d, U, nb, Q);
-                R u[3] = {Q[1], Q[2], Q[3]};
-                rot_z<R>((R)cr, (R)sr, u);
-                Q[1] = u[0];
-                Q[2] = u[1];
-                Q[3] = u[2];
-                const R wL = rec[kC3WL * st];
 #pragma unroll
-                for (int p = 0; p < 5; ++p) phi[p] = hi ? wL * P[p] + ((R)1 - wL) * Q[p] : wL * Q[p] + ((R)1 - wL) * P[p];
+            for (int p = 0; p < 5; ++p) {
+                const R pin = hi ? wL * P[p] + ((R)1 - wL) * Q[p] : wL * Q[p] + ((R)1 - wL) * P[p];
+                phi[p] = wall ? pw[p] : pin;
             }
 #pragma unroll
             for (int p = 0; p < 5; ++p) {
@@ -204,10 +221,9 @@ __global__ void __launch_bounds__(256) k_c3_grad(Domain d, Curv3Geo g, const R *
     }
 }
 
-// Primitives and gradients of cell c from the scratch buffers, as the image
-// rotated by (cr, sr) about z.
+// Primitives and gradients of cell c from the scratch buffers.
 template <typename R>
-__device__ inline void c3_view(const Domain &d, const Curv3Geo &g, int64_t c, R cr, R sr, R (&P)[5], R (&G)[5][3]) {
+__device__ inline void c3_load(const Domain &d, const Curv3Geo &g, int64_t c, R (&P)[5], R (&G)[5][3]) {
     const R *pr = (const R *)g.prim, *gr = (const R *)g.grad;
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
@@ -215,6 +231,12 @@ __device__ inline void c3_view(const Domain &d, const Curv3Geo &g, int64_t c, R 
 #pragma unroll
         for (int a = 0; a < 3; ++a) G[p][a] = gr[(p * 3 + a) * d.cells + c];
     }
+}
+
+// The loaded primitives and gradients of a cell as its image rotated by
+// (cr, sr) about z.
+template <typename R>
+__device__ inline void c3_rotate(R cr, R sr, R (&P)[5], R (&G)[5][3]) {
     if (sr == (R)0 && cr == (R)1) return;
     R u[3] = {P[1], P[2], P[3]};
     rot_z(cr, sr, u);
@@ -249,18 +271,49 @@ __device__ inline void c3_view(const Domain &d, const Curv3Geo &g, int64_t c, R 
 
 template <typename R, bool DEV, bool TL>
 __global__ void __launch_bounds__(256) k_c3_flux(Domain d, Curv3Geo g, const R *__restrict__ U) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= g.nfaces) return;
-    int a = 0;
-    int64_t f = t;
-    while (a < 2 && f >= g.sf[a]) {
-        f -= g.sf[a];
-        ++a;
-    }
+    // 32-bit index arithmetic: at most 2^28 cells, so fewer than 2^31 faces
+    const int t = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+    if (t >= (int)g.nfaces) return;
+    const int sf0 = (int)g.sf[0], sf1 = (int)g.sf[1];
+    const int a = t < sf0 ? 0 : (t < sf0 + sf1 ? 1 : 2);  // face family: normal index direction
+    const int f = t - (a == 0 ? 0 : (a == 1 ? sf0 : sf0 + sf1));
     const int nx = d.n[0] + (a == 0), ny = d.n[1] + (a == 1);
-    const int q[3] = {(int)(f % nx), (int)((f / nx) % ny), (int)(f / ((int64_t)nx * ny))};
-    const R *rec = (const R *)g.f[a] + f;
-    const int64_t st = g.sf[a];
+    const int fr = f / nx;
+    const int qx = f % nx, qy = fr % ny, qz = fr / ny;
+    const int qa = a == 0 ? qx : (a == 1 ? qy : qz);
+    const R *rec = (const R *)pick3(a, g.f) + f;
+    const int64_t st = pick3(a, g.sf);
+    const int na = pick3(a, d.n);
+    const bool per = pick3(a, d.periodic) != 0;
+    const bool interior = per || (qa > 0 && qa < na);
+    const bool low = qa == 0;  // wall faces: on the low side the fluid cell is the high one
+    // The low and high cells (images rotated by -alpha at face 0 and +alpha
+    // at face n of a periodic axis); at a wall both are clamped to the fluid
+    // cell.  Every load below is issued for every face, before any branch,
+    // so one round trip serves the face; the interior and the wall flux are
+    // both evaluated and the face's own one kept.
+    int la = qa - 1, ha = qa;  // index of the low and the high cell along a
+    R cl = (R)1, sl = (R)0, ch = (R)1, sh = (R)0;
+    const R rca = (R)pick3(a, g.rc), rsa = (R)pick3(a, g.rs);
+    if (la < 0) {
+        la = per ? la + na : 0;
+        cl = per ? rca : (R)1;
+        sl = per ? -rsa : (R)0;
+    }
+    if (ha >= na) {
+        ha = per ? ha - na : na - 1;
+        ch = per ? rca : (R)1;
+        sh = per ? rsa : (R)0;
+    }
+    const int64_t clo = c3_cell(d, a == 0 ? la : qx, a == 1 ? la : qy, a == 2 ? la : qz);
+    const int64_t chi = c3_cell(d, a == 0 ? ha : qx, a == 1 ? ha : qy, a == 2 ? ha : qz);
+    R PA[5], PB[5], GA[5][3], GB[5][3];
+    c3_load<R>(d, g, clo, PA, GA);
+    c3_load<R>(d, g, chi, PB, GB);
+    const int64_t N = d.fstride;
+    const int64_t cw = low ? chi : clo;  // the fluid cell of a wall face
+    const R rP = U[cw], eP = U[4 * N + cw];
+    const R mw[3] = {U[N + cw], U[2 * N + cw], U[3 * N + cw]};
     R e[3][3];
     e[0][0] = rec[kC3Nx * st];
     e[0][1] = rec[kC3Ny * st];
@@ -268,56 +321,37 @@ __global__ void __launch_bounds__(256) k_c3_flux(Domain d, Curv3Geo g, const R *
     e[1][0] = rec[kC3T1x * st];
     e[1][1] = rec[kC3T1y * st];
     e[1][2] = rec[kC3T1z * st];
+    const R dS = rec[kC3DS * st], dL = rec[kC3DL * st], dR = rec[kC3DR * st];
+    const R tl1 = rec[kC3TL1 * st], tl2 = rec[kC3TL2 * st], tr1 = rec[kC3TR1 * st], tr2 = rec[kC3TR2 * st];
     e[2][0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];  // t2 = n x t1
     e[2][1] = e[0][2] * e[1][0] - e[0][0] * e[1][2];
     e[2][2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
-    const R dS = rec[kC3DS * st];
     const Phys<R> &ph = make_phys<R>(d);
-    const int na = d.n[a];
-    const bool per = d.periodic[a];
     R F[5];
-    if (per || (q[a] > 0 && q[a] < na)) {
-        // low cell (image rotated by -alpha at face 0), high cell (image by +alpha at face n)
-        int lo[3] = {q[0], q[1], q[2]}, hi[3] = {q[0], q[1], q[2]};
-        lo[a] -= 1;
-        R cl = (R)1, sl = (R)0, ch = (R)1, sh = (R)0;
-        if (lo[a] < 0) {
-            lo[a] += na;
-            cl = (R)g.rc[a];
-            sl = -(R)g.rs[a];
-        }
-        if (hi[a] >= na) {
-            hi[a] -= na;
-            ch = (R)g.rc[a];
-            sh = (R)g.rs[a];
-        }
-        R PA[5], PB[5], GA[5][3], GB[5][3];
-        c3_view<R>(d, g, c3_cell(d, lo[0], lo[1], lo[2]), cl, sl, PA, GA);
-        c3_view<R>(d, g, c3_cell(d, hi[0], hi[1], hi[2]), ch, sh, PB, GB);
+    {
+        c3_rotate<R>(cl, sl, PA, GA);
+        c3_rotate<R>(ch, sh, PB, GB);
         Side<R, 3> A, B;
-        side_in_frame3<R>(PA, GA, e, rec[kC3TL1 * st], rec[kC3TL2 * st], A);
-        side_in_frame3<R>(PB, GB, e, rec[kC3TR1 * st], rec[kC3TR2 * st], B);
+        side_in_frame3<R>(PA, GA, e, tl1, tl2, A);
+        side_in_frame3<R>(PB, GB, e, tr1, tr2, B);
         const R up[3] = {c3_up<R>(g, 0), c3_up<R>(g, 1), c3_up<R>(g, 2)};
-        frame_flux3<R, DEV, TL>(A, B, rec[kC3DL * st], rec[kC3DR * st], e, up, d.force_pred != 0, dS, ph, F);
-    } else {
-        const bool low = q[a] == 0;  // wall on the low side: the fluid cell is the high one
-        int w[3] = {q[0], q[1], q[2]};
-        if (!low) w[a] -= 1;
-        const int64_t c = c3_cell(d, w[0], w[1], w[2]);
+        frame_flux3<R, DEV, TL>(A, B, dL, dR, e, up, d.force_pred != 0, dS, ph, F);
+    }
+    {
         const int side = 2 * a + (low ? 0 : 1);
-        const int64_t N = d.fstride;
-        const R rP = U[c];
-        const R m[3] = {U[N + c], U[2 * N + c], U[3 * N + c]};
         R ml[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) ml[k] = m[0] * e[k][0] + m[1] * e[k][1] + m[2] * e[k][2];
-        R G[5];
-        wall_flux<R, 3, DEV>(rP, ml, U[4 * N + c], low ? (R)-1 : (R)1, low ? rec[kC3DR * st] : rec[kC3DL * st],
-                             d.kind[side] == kIsothermal, wall_T<R>(d, side), ph, G);
-        F[0] = G[0] * dS;
+        for (int k = 0; k < 3; ++k) ml[k] = mw[0] * e[k][0] + mw[1] * e[k][1] + mw[2] * e[k][2];
+        R G[5], Fw[5];
+        const R Tw = sizeof(R) == 4 ? (R)pick6(side, d.Twf) : (R)pick6(side, d.Tw);
+        wall_flux<R, 3, DEV>(rP, ml, eP, low ? (R)-1 : (R)1, low ? dR : dL, pick6(side, d.kind) == kIsothermal, Tw,
+                             ph, G);
+        Fw[0] = G[0] * dS;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) F[1 + b] = (G[1] * e[0][b] + G[2] * e[1][b] + G[3] * e[2][b]) * dS;
-        F[4] = G[4] * dS;
+        for (int b = 0; b < 3; ++b) Fw[1 + b] = (G[1] * e[0][b] + G[2] * e[1][b] + G[3] * e[2][b]) * dS;
+        Fw[4] = G[4] * dS;
+#pragma unroll
+        for (int p = 0; p < 5; ++p) F[p] = interior ? F[p] : Fw[p];
     }
     R *out = (R *)g.flux;
 #pragma unroll
@@ -330,12 +364,15 @@ __global__ void __launch_bounds__(256) k_c3_update(Domain d, Curv3Geo g, const R
                                                    const uint32_t *__restrict__ ctr_in, uint32_t *__restrict__ ctr_out) {
     __shared__ double sred[kPartials * 4];
     const uint32_t key = *ctr_in;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;  // at most 2^28 cells
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (c < d.cells) {
-        const int i = (int)(c % d.n[0]), j = (int)((c / d.n[0]) % d.n[1]), k = (int)(c / ((int64_t)d.n[0] * d.n[1]));
+    if (c < (int)d.cells) {
+        const int i = c % d.n[0], jk = c / d.n[0], j = jk % d.n[1], k = jk / d.n[1];
         const int64_t N = d.fstride;
         const R *fl = (const R *)g.flux;
+        R old[5];  // loaded with the fluxes, ahead of the per-field rounding
+#pragma unroll
+        for (int p = 0; p < 5; ++p) old[p] = Uin[p * N + c];
         R div[5] = {0, 0, 0, 0, 0};
         int64_t base = 0;
 #pragma unroll
@@ -359,9 +396,8 @@ __global__ void __launch_bounds__(256) k_c3_update(Domain d, Curv3Geo g, const R
         for (int p = 0; p < 5; ++p) {
             const R src = (p >= 1 && p <= 3) ? Fb * c3_up<R>(g, p - 1) : (R)0;
             const R inc = dt_dV * div[p] + src;
-            const R old = Uin[p * N + c];
-            if (sizeof(R) == 4 && d.sround) Un[p] = sr_add(old, inc, sr_hash((uint32_t)c, key * 5u + p));
-            else Un[p] = old + inc;
+            if (sizeof(R) == 4 && d.sround) Un[p] = sr_add(old[p], inc, sr_hash((uint32_t)c, key * 5u + p));
+            else Un[p] = old[p] + inc;
             Uout[p * N + c] = Un[p];
         }
         if (RES) {
