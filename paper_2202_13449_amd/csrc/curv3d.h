@@ -157,8 +157,14 @@ __device__ inline void c3_prims(const Domain &d, const R *__restrict__ U, int64_
     for (int p = 1; p < 5; ++p) P[p] = U[p * N + c] * inv;
 }
 
+// Threads per block of the per-cell and per-face kernels.  The kernels are
+// bound by load latency at small sizes (28,800 cells for the Sec. 4.5
+// annulus); one-wavefront blocks spread the waves, and their memory
+// traffic, over every CU.
+constexpr int kC3Threads = 64;
+
 template <typename R, bool DEV>
-__global__ void __launch_bounds__(256) k_c3_grad(Domain d, Curv3Geo g, const R *__restrict__ U) {
+__global__ void __launch_bounds__(kC3Threads) k_c3_grad(Domain d, Curv3Geo g, const R *__restrict__ U) {
     // 32-bit index arithmetic: a body-fitted mesh holds at most 2^28 cells
     const int c = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
     if (c >= (int)d.cells) return;
@@ -270,7 +276,7 @@ __device__ inline void c3_rotate(R cr, R sr, R (&P)[5], R (&G)[5][3]) {
 }
 
 template <typename R, bool DEV, bool TL>
-__global__ void __launch_bounds__(256) k_c3_flux(Domain d, Curv3Geo g, const R *__restrict__ U) {
+__global__ void __launch_bounds__(kC3Threads) k_c3_flux(Domain d, Curv3Geo g, const R *__restrict__ U) {
     // 32-bit index arithmetic: at most 2^28 cells, so fewer than 2^31 faces
     const int t = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
     if (t >= (int)g.nfaces) return;
@@ -359,7 +365,7 @@ __global__ void __launch_bounds__(256) k_c3_flux(Domain d, Curv3Geo g, const R *
 }
 
 template <typename R, bool DEV, bool RES>
-__global__ void __launch_bounds__(256) k_c3_update(Domain d, Curv3Geo g, const R *__restrict__ Uin,
+__global__ void __launch_bounds__(kC3Threads) k_c3_update(Domain d, Curv3Geo g, const R *__restrict__ Uin,
                                                    R *__restrict__ Uout, double *__restrict__ parts,
                                                    const uint32_t *__restrict__ ctr_in, uint32_t *__restrict__ ctr_out) {
     __shared__ double sred[kPartials * 4];

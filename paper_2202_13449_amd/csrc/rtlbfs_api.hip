@@ -299,7 +299,7 @@ int curv_blocks(const rtlbfs_mesh &m, int tile) {
 
 // Blocks of one step launch of the handle (rows of residual partials).
 int handle_blocks(const rtlbfs_t h, int tile) {
-    if (h->curv3) return (int)((h->lay.cells + 255) / 256);
+    if (h->curv3) return (int)((h->lay.cells + kC3Threads - 1) / kC3Threads);
     return h->curv ? curv_blocks(h->mesh, tile) : step_blocks(h->mesh, tile);
 }
 
@@ -307,11 +307,12 @@ template <typename R, bool DEV, bool TL>
 hipError_t launch_curv3(rtlbfs_t h, int src, bool res, hipStream_t s) {
     const R *Uin = (const R *)h->U(src);
     R *Uout = (R *)h->U(src ^ 1);
-    const int cb = (int)((h->lay.cells + 255) / 256), fb = (int)((h->c3.nfaces + 255) / 256);
-    k_c3_grad<R, DEV><<<cb, 256, 0, s>>>(h->dom, h->c3, Uin);
-    k_c3_flux<R, DEV, TL><<<fb, 256, 0, s>>>(h->dom, h->c3, Uin);
-    if (res) k_c3_update<R, DEV, true><<<cb, 256, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
-    else k_c3_update<R, DEV, false><<<cb, 256, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
+    constexpr int nt = kC3Threads;
+    const int cb = (int)((h->lay.cells + nt - 1) / nt), fb = (int)((h->c3.nfaces + nt - 1) / nt);
+    k_c3_grad<R, DEV><<<cb, nt, 0, s>>>(h->dom, h->c3, Uin);
+    k_c3_flux<R, DEV, TL><<<fb, nt, 0, s>>>(h->dom, h->c3, Uin);
+    if (res) k_c3_update<R, DEV, true><<<cb, nt, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
+    else k_c3_update<R, DEV, false><<<cb, nt, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
     return hipGetLastError();
 }
 
@@ -606,7 +607,7 @@ Curv3Layout make_curv3_layout(const int n[3], int precision) {
     off += align256((size_t)15 * cells * es);
     l.off_flux = off;
     off += align256((size_t)5 * nfaces * es);
-    l.nparts = std::max<int>(kRedBlocks, (int)((cells + 255) / 256));
+    l.nparts = std::max<int>(kRedBlocks, (int)((cells + kC3Threads - 1) / kC3Threads));  // one per update block
     l.off_parts = off;
     off += align256(sizeof(double) * (size_t)l.nparts * 8);
     l.off_red = off;
@@ -949,7 +950,7 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
     out->precision = h->opts.precision;
     for (int t = 0; t < kNumTiles2; ++t) out->tune_ms[t] = h->tune_ms[t];
     if (h->curv3) {
-        out->tile_x = 256;  // one thread per cell or face, 256 per block
+        out->tile_x = kC3Threads;  // one thread per cell or face, kC3Threads per block
         out->tile_y = 1;
         out->tile_z = 1;
         out->steps_per_launch = 1;
