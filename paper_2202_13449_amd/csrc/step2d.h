@@ -22,17 +22,24 @@
 //      sub-step; to HBM, with the FP64 partial sums of Eq. 65 on residual
 //      steps, for the last one.
 // The block has one thread per face of the largest update region, so every
-// phase is a single straight pass.  The face pass comes in two layouts:
-//   - shared (one-step launches): x- and y-faces side by side, rounded up to
-//     whole wavefronts once; all interior faces run one code path with the
-//     face frame chosen per lane (LDS addresses and selects);
-//   - split (two-step launches): the x-faces and the y-faces each in whole
-//     wavefronts, so the axis is wave-uniform and each side runs code with its
-//     frame fixed (compile-time offsets, no per-lane selects between x and y).
-// The split costs idle lanes where a face count is not a multiple of 64 and
-// pays where one tile per CU makes the per-lane instruction count the step's
-// time; a two-step launch is chosen for exactly such small domains, and for
-// its 20 x 20 first region (420 + 420 faces) the split adds no wavefront.
+// phase is a single straight pass.  The face pass comes in three layouts:
+//   - shared: x- and y-faces side by side, rounded up to whole wavefronts
+//     once; all interior faces run one code path with the face frame chosen
+//     per lane (LDS addresses and selects);
+//   - split: the x-faces and the y-faces each in whole wavefronts, so the
+//     axis is wave-uniform and each side runs code with its frame fixed
+//     (compile-time offsets, no per-lane selects between x and y);
+//   - hybrid: whole wavefronts of x-faces, one wavefront holding the x tail
+//     and the y tail (shared code), then whole wavefronts of y-faces.  It
+//     uses the shared layout's wavefront count when the two tails fit in
+//     one wavefront, with every other wavefront running axis-fixed code.
+// One-step launches take the hybrid layout where the tails fit, the split
+// one where there are no tails, and the shared one otherwise: large domains keep many blocks per CU, where the
+// total instruction count sets the time and idle lanes cost.  Two-step
+// launches take the split layout: they serve small domains, one tile per
+// CU, where the wavefronts on the busiest SIMD set the time; for the 20 x 20
+// first region of a 16 x 16 tile (420 + 420 faces) the split adds no
+// wavefront.
 // Within a wavefront the phases avoid divergence: neighbour values are read
 // unconditionally and chosen by selects rather than by branches around single
 // LDS reads.
@@ -48,24 +55,29 @@ constexpr int region_faces() {
     return (UX + 1) * UY + UX * (UY + 1);
 }
 
-// Threads of a UX x UY update region's face pass: all faces in whole
-// wavefronts (shared layout), or the x-faces and then the y-faces each in
-// whole wavefronts (split layout).
-template <int UX, int UY, bool SPLIT>
-constexpr int region_face_threads() {
-    return SPLIT ? ((UX + 1) * UY + 63) / 64 * 64 + (UX * (UY + 1) + 63) / 64 * 64
-                 : (region_faces<UX, UY>() + 63) / 64 * 64;
+// Face-pass layouts: shared, split, hybrid (described at the top of this file).
+enum : int { kFacesShared = 0, kFacesSplit = 1, kFacesHybrid = 2 };
+
+// Layout of the face pass of a UX x UY update region in a launch of NSUB
+// steps.  Without tails (both face counts multiples of 64) the split layout
+// has no idle lane and is taken.
+template <int UX, int UY, int NSUB>
+constexpr int face_layout() {
+    constexpr int tails = ((UX + 1) * UY) % 64 + (UX * (UY + 1)) % 64;
+    return NSUB == 2 || tails == 0 ? kFacesSplit : (tails <= 64 ? kFacesHybrid : kFacesShared);
 }
 
-// The face pass of a two-step launch uses the split layout.
-template <int NSUB>
-constexpr bool split_faces() {
-    return NSUB == 2;
+// Threads of a UX x UY update region's face pass in the given layout.
+template <int UX, int UY, int LAYOUT>
+constexpr int region_face_threads() {
+    return LAYOUT == kFacesSplit ? ((UX + 1) * UY + 63) / 64 * 64 + (UX * (UY + 1) + 63) / 64 * 64
+                                 : (region_faces<UX, UY>() + 63) / 64 * 64;
 }
 
 template <int TX, int TY, int NSUB = 1>
 constexpr int tile2_threads() {
-    return region_face_threads<TX + 4 * (NSUB - 1), TY + 4 * (NSUB - 1), split_faces<NSUB>()>();
+    constexpr int UX = TX + 4 * (NSUB - 1), UY = TY + 4 * (NSUB - 1);  // largest update region
+    return region_face_threads<UX, UY, face_layout<UX, UY, NSUB>()>();
 }
 
 // Block -> tile order that keeps each XCD on a contiguous band of tiles.
@@ -100,7 +112,7 @@ struct SubView {
     int gsx, gsy, gx0, gy0;
 };
 
-template <typename R, bool DEV, bool TL, int UX, int UY, bool LAST, bool RES, int NT, bool SPLIT>
+template <typename R, bool DEV, bool TL, int UX, int UY, bool LAST, bool RES, int NT, int LAYOUT>
 __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, const SubView<R> &v, R *sp_next,
                                            const R *swT, const int *swIso, R *__restrict__ Uout,
                                            double *__restrict__ part, double *sred, uint32_t step_key) {
@@ -108,9 +120,8 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
     constexpr int GX = UX + 2, GY = UY + 2;  // gradients with a 1-cell halo
     constexpr int NFX = (UX + 1) * UY;
     constexpr int NF = region_faces<UX, UY>();
-    constexpr int WX = (NFX + 63) / 64 * 64;  // split layout: threads of the x-faces
     constexpr int PF = PX * PY, GF = GX * GY;  // field strides in sp and sg
-    static_assert(GX * GY <= NT && region_face_threads<UX, UY, SPLIT>() <= NT && UX * UY <= NT,
+    static_assert(GX * GY <= NT && region_face_threads<UX, UY, LAYOUT>() <= NT && UX * UY <= NT,
                   "every phase is one pass of the block");
     const int nx = d.n[0], ny = d.n[1];
     const int64_t N = d.fstride;
@@ -233,11 +244,24 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
         v.sf[2 * NF + fo] = (isx ? G[2] : G[1]) * area;
         v.sf[3 * NF + fo] = G[3] * area;
     };
-    if constexpr (SPLIT) {
-        // threads [0, WX) take the x-faces, [WX, WX + NF - NFX) the y-faces;
-        // the wavefront index, read as a scalar, makes the branch uniform
-        if (__builtin_amdgcn_readfirstlane(tid >> 6) < WX / 64) face(true, tid);
+    // The wavefront index, read as a scalar, makes the layout's branches
+    // uniform.
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if constexpr (LAYOUT == kFacesSplit) {
+        // threads [0, WX) take the x-faces, [WX, WX + NF - NFX) the y-faces
+        constexpr int WX = (NFX + 63) / 64 * 64;
+        if (wave < WX / 64) face(true, tid);
         else face(false, tid - WX);
+    } else if constexpr (LAYOUT == kFacesHybrid) {
+        // wavefronts [0, XW): x-faces [0, 64 XW); wavefront XW: lanes [0, TXT)
+        // the x-faces from 64 XW, lanes [TXT, TXT + TYT) the y-faces [0, TYT);
+        // the wavefronts after it: y-faces from TYT
+        constexpr int XW = NFX / 64, TXT = NFX % 64, TYT = (NF - NFX) % 64;
+        static_assert(TXT + TYT > 0 && TXT + TYT <= 64, "both tails fit in one wavefront");
+        const int lane = tid - 64 * XW;
+        if (wave < XW) face(true, tid);
+        else if (wave > XW) face(false, TYT + tid - 64 * (XW + 1));
+        else if (lane < TXT + TYT) face(lane < TXT, lane < TXT ? 64 * XW + lane : lane - TXT);
     } else {
         // threads [0, NFX) take the x-faces, [NFX, NF) the y-faces
         if (tid < NF) face(tid < NFX, tid < NFX ? tid : tid - NFX);
@@ -422,21 +446,21 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     }
     __syncthreads();
 
-    constexpr bool SPL = split_faces<NSUB>();
+    constexpr int LA = face_layout<U0X, U0Y, NSUB>(), LB = face_layout<TX, TY, NSUB>();
     if constexpr (NSUB == 1) {
         const SubView<R> v{spA, sg, sf, sc, 0, TX, SCF, sgx, sgy, LX, LY, 0, 0};
-        substep_2d<R, DEV, TL, TX, TY, true, RES, NT, SPL>(d, i0, j0, v, nullptr, swT, swIso, Uout, part, sred,
-                                                           step_key);
+        substep_2d<R, DEV, TL, TX, TY, true, RES, NT, LB>(d, i0, j0, v, nullptr, swT, swIso, Uout, part, sred,
+                                                          step_key);
     } else {
         const SubView<R> va{spA, sg, sf, sc, 0, U0X, SCF, sgx, sgy, LX, LY, 0, 0};
-        substep_2d<R, DEV, TL, U0X, U0Y, false, false, NT, SPL>(d, i0 - 2, j0 - 2, va, spB, swT, swIso, nullptr,
-                                                                nullptr, sred, step_key);
+        substep_2d<R, DEV, TL, U0X, U0Y, false, false, NT, LA>(d, i0 - 2, j0 - 2, va, spB, swT, swIso, nullptr,
+                                                               nullptr, sred, step_key);
         __syncthreads();
         // second sub-step: primitives from spB, old state inside sc at (2, 2),
         // geometry shifted by the two cells the region shrank by
         const SubView<R> vb{spB, sg, sf, sc, 2 * U0X + 2, U0X, SCF, sgx, sgy, LX, LY, 2, 2};
-        substep_2d<R, DEV, TL, TX, TY, true, RES, NT, SPL>(d, i0, j0, vb, nullptr, swT, swIso, Uout, part, sred,
-                                                           step_key + 1u);
+        substep_2d<R, DEV, TL, TX, TY, true, RES, NT, LB>(d, i0, j0, vb, nullptr, swT, swIso, Uout, part, sred,
+                                                          step_key + 1u);
     }
 }
 
