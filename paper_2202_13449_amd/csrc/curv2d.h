@@ -251,12 +251,16 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
     }
     __syncthreads();
 
-    // ---- faces
-    if (tid < NF) {
-        const bool isi = tid < NFX;
-        const int q = tid - NFX;
-        const int lx = isi ? tid % (TX + 1) : q % TX;
-        const int ly = isi ? tid / (TX + 1) : q / TX;
+    // ---- faces.  face(isi, q) handles face q of its family (i-faces, then
+    // j-faces in sf); it is inlined at each call, so a literal isi folds every
+    // choice between the families.  Hybrid layout (as in the Cartesian step):
+    // whole wavefronts of i-faces, one wavefront with the i tail and the
+    // j tail, then whole wavefronts of j-faces; shared layout where the tails
+    // do not fit in one wavefront.
+    auto face = [&](bool isi, int q) __attribute__((always_inline)) {
+        if (q >= (isi ? NFX : NF - NFX)) return;
+        const int lx = isi ? q % (TX + 1) : q % TX;
+        const int ly = isi ? q / (TX + 1) : q / TX;
         const int gx_ = i0 + lx, gy_ = j0 + ly;  // face index (i, j); the tile's cells need faces up to n
         const bool ok = isi ? (gx_ <= nx && gy_ < ny) : (gx_ < nx && gy_ <= ny);
         if (ok) {
@@ -336,9 +340,20 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
                     for (int p = 0; p < 4; ++p) Fg[p] = so * Fo[p];
                 }
             }
+            const int fo = isi ? q : NFX + q;
 #pragma unroll
-            for (int p = 0; p < 4; ++p) sf[p * NF + tid] = Fg[p];
+            for (int p = 0; p < 4; ++p) sf[p * NF + fo] = Fg[p];
         }
+    };
+    constexpr int XW = NFX / 64, TXT = NFX % 64, TYT = (NF - NFX) % 64;
+    if constexpr (TXT + TYT > 0 && TXT + TYT <= 64) {
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // a scalar: uniform branches
+        const int lane = tid - 64 * XW;
+        if (wave < XW) face(true, tid);
+        else if (wave > XW) face(false, TYT + tid - 64 * (XW + 1));
+        else if (lane < TXT + TYT) face(lane < TXT, lane < TXT ? 64 * XW + lane : lane - TXT);
+    } else {
+        if (tid < NF) face(tid < NFX, tid < NFX ? tid : tid - NFX);
     }
     __syncthreads();
 
