@@ -5,7 +5,9 @@
 //
 // One launch advances a TX x TY tile of cells by one step, in four phases
 // separated by workgroup barriers, all through LDS (one thread per face of
-// the tile, so each phase is one pass of the block):
+// the tile, so each phase is one pass of the block; the faces in the hybrid
+// layout of the Cartesian step, whole wavefronts of i-faces and of j-faces
+// around one wavefront holding both tails):
 //   load       conserved state of the tile plus a 2-cell halo, primitives;
 //   gradients  Eq. 55 for the tile plus a 1-cell halo: (1/dV) sum over the
 //              cell's four faces of phi_S n_out dS, with Eq. 56 face values on
