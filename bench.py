@@ -533,6 +533,128 @@ def steady_bench(rt, torch, steps, warmup, tol=1e-8, max_steps=4_000_000, chunk=
     return res
 
 
+# High-Ra cavities of Sec. 4.2 (Tables 2 and 3): the paper gives the mesh
+# size and the wall distance of the first cell (0.0004 L on 300^2 at Ra =
+# 1e7, 0.0002 L on 400^2 at Ra = 1e8) but not the stretching law; the Eq. 74
+# tanh law is used with phi solved for that first cell.  Printed values: the
+# "Present" column and the pseudospectral column (Quere) of each table.
+TABLES_2_3 = {
+    1e7: {"n": 300, "first_over_L": 4e-4,
+          "present": {"psi_max": 30.121, "psi_x": 0.0862, "psi_y": 0.5584, "nu_half": 16.510,
+                      "u_max": 148.08, "u_y": 0.8802, "v_max": 699.21, "v_x": 0.0213},
+          "pseudospectral": {"psi_max": 30.165, "psi_x": 0.086, "psi_y": 0.556, "nu_half": 16.52,
+                             "u_max": 148.59, "u_y": 0.879, "v_max": 699.18, "v_x": 0.021}},
+    1e8: {"n": 400, "first_over_L": 2e-4,
+          "present": {"psi_max": 53.823, "psi_x": 0.0488, "psi_y": 0.5516, "nu_half": 30.220,
+                      "u_max": 312.734, "u_y": 0.9303, "v_max": 2222.8, "v_x": 0.0118},
+          "pseudospectral": {"psi_max": 53.85, "psi_x": 0.048, "psi_y": 0.553, "nu_half": 30.225,
+                             "u_max": 321.9, "u_y": 0.928, "v_max": 2222.0, "v_x": 0.012}},
+}
+HIGHRA_BUDGET_S = 240.0   # wall-clock budget per case (--budget-s)
+HIGHRA_CASES = (1e7, 1e8)  # --ra selects one
+
+
+def stretch_for_first_cell(rt, n, first_over_L):
+    """phi of the Eq. 74 tanh law whose first cell is first_over_L of the
+    length (bisection; the length in first-cell units grows with phi)."""
+    lo, hi = 0.1, 6.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if 1.0 / rt.mesh_nodes(n, mid)[1] > first_over_L:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def _peak(xs, ys):
+    """Maximum of sampled ys(xs) refined by the parabola through the largest
+    sample and its two neighbours: (value, position)."""
+    k = int(np.argmax(ys))
+    if k == 0 or k == len(ys) - 1:
+        return float(ys[k]), float(xs[k])
+    x0, x1, x2 = xs[k - 1], xs[k], xs[k + 1]
+    y0, y1, y2 = ys[k - 1], ys[k], ys[k + 1]
+    d0, d2 = (y0 - y1) / (x0 - x1), (y2 - y1) / (x2 - x1)
+    a = (d2 - d0) / (x2 - x0)            # curvature of the parabola
+    if a >= 0:
+        return float(y1), float(x1)
+    b = d0 - a * (x0 - x1)               # slope at x1
+    xm = x1 - b / (2 * a)
+    return float(y1 - b * b / (4 * a)), float(xm)
+
+
+def table23_quantities(rt, s, n, phi):
+    """The quantities of Tables 2 and 3 from the absolute primitive fields:
+    |psi/chi|_max and its position (psi = integral of u dy from the bottom
+    wall, at the cell columns), Nu along x = L/2 (integral of rho u T -
+    chi dT/dx over y, divided by chi; dT = 1), and the maxima of u L/chi
+    along x = L/2 and v L/chi along y = L/2 with their positions (parabolic
+    refinement around the largest cell value)."""
+    x, L = rt.mesh_nodes(n, phi)
+    xc, dx = 0.5 * (x[:-1] + x[1:]), np.diff(x)
+    chi = s.info.chi
+    rho, u, v, T = (s.grid(s.field(f)) for f in range(4))  # [row j (y), column i (x)]
+    m = n // 2  # x = L/2 lies between columns m - 1 and m (symmetric mesh)
+    q = 0.5 * (rho[:, m - 1] * u[:, m - 1] * T[:, m - 1] + rho[:, m] * u[:, m] * T[:, m])
+    q -= chi * (T[:, m] - T[:, m - 1]) / (xc[m] - xc[m - 1])
+    nu_half = float(np.sum(q * dx) / chi)
+    um, uy = _peak(xc / L, 0.5 * (u[:, m - 1] + u[:, m]) * L / chi)
+    vm, vx = _peak(xc / L, 0.5 * (v[m - 1, :] + v[m, :]) * L / chi)
+    psi = np.abs(np.cumsum(u * dx[:, None], axis=0)) / chi  # at the top face of each cell
+    j, i = np.unravel_index(int(np.argmax(psi)), psi.shape)
+    return {"psi_max": float(psi[j, i]), "psi_x": float(xc[i] / L), "psi_y": float(x[j + 1] / L),
+            "nu_half": nu_half, "u_max": um, "u_y": uy, "v_max": vm, "v_x": vx}
+
+
+def dhc_highra_bench(rt, torch, steps, warmup, tol=1e-8, chunk=100_000, plateau=2e-5):
+    """Cavities of Tables 2 and 3 in FP32 deviation storage, run from rest
+    (plus 1e-6 noise) to steady state or until the time budget per case is
+    spent, with a progress line every 10 chunks; then the table quantities
+    beside the printed ones.  Steady: both Eq. 65 ratios below tol, or the
+    hot-wall Nusselt number changing by less than `plateau` (relative) over
+    three successive progress lines.  Stochastically rounded FP32 holds the
+    Eq. 65 ratios at a floor of a few 1e-8 once the flow is steady, which the
+    plateau test allows for."""
+    out = {"workload": "2D cavity at Ra 1e7 (300^2) and 1e8 (400^2), Sec. 4.2 Tables 2-3"}
+    for Ra in HIGHRA_CASES:
+        case = TABLES_2_3[Ra]
+        n = case["n"]
+        phi = stretch_for_first_cell(rt, n, case["first_over_L"])
+        s = rt.Solver(2, (n, n), (phi, phi), KIND, TDEV, GAXIS, Ra=Ra, Pr=PR, Ma=MA, precision=rt.FP32_DEV,
+                      seed=1, noise_amp=1e-6, residual_every=chunk, mass_fix_every=1000)
+        steps_per_tstar = s.info.L / (MA * s.info.dt)
+        done, t0, res = 0, time.perf_counter(), (1.0, 1.0)
+        history, steady = [], False
+        while time.perf_counter() - t0 < HIGHRA_BUDGET_S:
+            s.step(chunk)
+            done += chunk
+            res = s.residual()
+            if max(res) < tol:
+                steady = True
+            if done % (10 * chunk) == 0 or steady:
+                nu = s.nusselt()["hot_avg"]
+                history.append(nu)
+                print(f"# Ra {Ra:.0e}: {done} steps (t* {done / steps_per_tstar:.1f}), residual {res[0]:.2e} "
+                      f"{res[1]:.2e}, Nu hot {nu:.5f}, {time.perf_counter() - t0:.0f} s", flush=True)
+                last = history[-4:]
+                if len(last) == 4 and max(abs(a - b) for a, b in zip(last, last[1:])) < plateau * abs(nu):
+                    steady = True
+            if steady:
+                break
+        got = table23_quantities(rt, s, n, phi)
+        pres = case["present"]
+        out[f"ra{Ra:.0e}"] = {"n": n, "phi": phi, "L": s.info.L, "steps": done, "tstar": done / steps_per_tstar,
+                              "residual": list(res), "steady": steady,
+                              "seconds": time.perf_counter() - t0, "ours": got, "paper_present": pres,
+                              "paper_pseudospectral": case["pseudospectral"],
+                              "rel_diff_vs_present": {k: (got[k] - pres[k]) / pres[k] for k in pres},
+                              "nu_walls": s.nusselt(), "tile": list(launch_shape(s.info))}
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 # Body-fitted meshes (Sec. 4.3).  Flops per cell-update of the curvilinear
 # step kernel: two faces (545 FP32-deviation / 523 FP64-plain each, the
 # library's frame functions counted by tests/test_flops_cpu.py) + Eq. 55
@@ -755,7 +877,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
     ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods",
-                                                           "stability", "cylinder", "cylinder_table4", "annulus", "annulus_table7"],
+                                                           "stability", "cylinder", "cylinder_table4", "annulus", "annulus_table7",
+                                                           "dhc_highra"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
                          "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
                          "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5; "
@@ -763,10 +886,20 @@ def main():
                          "stability: the stability maps of Figs. 4-5 as batched runs; cylinder: the body-fitted "
                          "step on the 450x300 O-mesh of Sec. 4.3; cylinder_table4: Table 4, Gr 0..1600; "
                          "annulus: the body-fitted 3D step on the 120x1x240 wedge of Sec. 4.5; "
-                         "annulus_table7: that annulus against Table 7")
+                         "annulus_table7: that annulus against Table 7; dhc_highra: the cavities of Tables 2-3 "
+                         "(Ra 1e7 on 300^2, Ra 1e8 on 400^2) to steady state or --budget-s")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
+    ap.add_argument("--ra", type=float, default=None, help="dhc_highra: run only this Rayleigh number (1e7 or 1e8)")
+    ap.add_argument("--budget-s", type=float, default=None, help="dhc_highra: wall-clock seconds per case")
     args = ap.parse_args()
+    global HIGHRA_CASES, HIGHRA_BUDGET_S
+    if args.ra is not None:
+        if args.ra not in TABLES_2_3:
+            ap.error("--ra must be 1e7 or 1e8")
+        HIGHRA_CASES = (args.ra,)
+    if args.budget_s is not None:
+        HIGHRA_BUDGET_S = args.budget_s
     if args.gpus != 1:
         print("bench.py measures one GPU: the RTLBFS step of one domain runs on a single MI355X; "
               "multi-GPU sharding is not implemented (use --gpus 1)", file=sys.stderr)
@@ -795,7 +928,7 @@ def main():
               "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench,
               "stability": stability_bench, "cylinder": cylinder_bench,
               "cylinder_table4": cylinder_table4_bench, "annulus": annulus_bench,
-              "annulus_table7": annulus_table7_bench}[args.workload]
+              "annulus_table7": annulus_table7_bench, "dhc_highra": dhc_highra_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
     cells = N_CELLS_SIDE * N_CELLS_SIDE
