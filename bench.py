@@ -13,6 +13,7 @@ workload.  Inputs are resident in HBM before the timed region starts.
 Prints one JSON line.
 """
 import argparse
+import math
 import json
 import os
 import sys
@@ -402,12 +403,16 @@ def hill_bench(rt, torch, steps, warmup, sizes=(80, 120, 160, 200, 240)):
     return out
 
 
+TABLE6 = {"tlbfs": 60585.58, "rtlbfs": 58864.12, "ratio": 0.9716}  # serial CPU, t* = 1, 80^3, Ra = 1e6
+
+
 def methods_bench(rt, torch, steps, warmup):
     """Cost of the two interior-face fluxes on the same workloads (the paper's
     Table 6 compares RTLBFS with TLBFS by CPU time): the 256^2 tanh cavity in
     FP32 deviation and FP64 plain storage, and the 192^3 tanh cube in FP32,
     each timed as whole graph-replayed steps with the tile fixed to the one
-    the autotuner picks for RTLBFS."""
+    the autotuner picks for RTLBFS; then Table 6's own case, one t* on the
+    80^3 cube at Ra = 1e6 in FP64."""
     out = {"workload": "RTLBFS vs TLBFS step cost"}
     for name, prec in (("cavity256_fp32", rt.FP32_DEV), ("cavity256_fp64", rt.FP64_PLAIN)):
         res = {}
@@ -433,6 +438,22 @@ def methods_bench(rt, torch, steps, warmup):
         torch.cuda.empty_cache()
     res["rtlbfs_over_tlbfs"] = res["rtlbfs"]["ms_per_step"] / res["tlbfs"]["ms_per_step"]
     out["cube192_fp32"] = res
+    # Table 6's own case: t_cost of one dimensionless time unit t* = V_c t / L
+    # on the 80^3 tanh cube (phi = 1.8) at Ra = 1e6, in FP64 (the paper's
+    # arithmetic), started from the state after 2,000 steps.
+    res = {}
+    for mname, method in (("rtlbfs", rt.METHOD_RTLBFS), ("tlbfs", rt.METHOD_TLBFS)):
+        s = rt.Solver(3, (80, 80, 80), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=1e6,
+                      Pr=0.71, Ma=MA, precision=rt.FP64_PLAIN, seed=1, noise_amp=1e-6, method=method)
+        s.step(2000)
+        n_tstar = int(math.ceil(s.info.L / (MA * s.info.dt)))
+        ms = timed(torch, s, n_tstar)
+        res[mname] = {"steps_per_tstar": n_tstar, "t_cost_s": ms * n_tstar * 1e-3}
+        del s
+        torch.cuda.empty_cache()
+    res["rtlbfs_over_tlbfs"] = res["rtlbfs"]["t_cost_s"] / res["tlbfs"]["t_cost_s"]
+    res["paper_table6_serial_cpu_s"] = TABLE6
+    out["cube80_fp64_tstar1"] = res
     return out
 
 
