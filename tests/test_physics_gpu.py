@@ -1,5 +1,8 @@
 """Steady-state physics of the GPU path against values the paper prints.
 
+Sec. 4.2, Table 1: the square cavity at Ra = 1e3 ... 1e6 on the paper's
+uniform meshes, FP64 (tests/golden/table1_dhc.txt).
+
 Sec. 4.4, Table 5: natural convection in a cubic cavity on an 80^3 tanh mesh
 (phi = 1.8), Pr = 0.71, V_c = 0.1, hot wall at x = L, gravity along -z.  The
 FP32 deviation path is run to steady state at Ra = 1e5 and compared with the
@@ -39,6 +42,56 @@ def peak(xc, f):
     a, b, c = np.linalg.solve(A, f[k - 1:k + 2])
     xm = -b / (2 * a)
     return xm, a * xm * xm + b * xm + c
+
+
+TABLE1 = os.path.join(os.path.dirname(__file__), "golden", "table1_dhc.txt")
+TABLE1_MESH = {1e3: 100, 1e4: 150, 1e5: 200, 1e6: 250}  # Sec. 4.2: uniform meshes per Ra
+
+
+def table1():
+    rows = {}
+    with open(TABLE1) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [float(t) for t in line.split()]
+            rows[v[0]] = dict(u_max=v[1], y=v[2], v_max=v[3], x=v[4], Nu_a=v[5])
+    return rows
+
+
+@pytest.mark.parametrize("Ra", sorted(TABLE1_MESH))
+def test_square_cavity_matches_table1(Ra):
+    """Sec. 4.2, Table 1: the square cavity at Ra = 1e3 ... 1e6 on the paper's
+    uniform meshes (100^2 ... 250^2), FP64 plain storage, run until both
+    Eq. 65 ratios are below 1e-9.  Compared with the 'Present' column: the
+    maximum of u L / chi on x = L/2 and its height, the maximum of v L / chi
+    on y = L/2 and its abscissa, and the average Nusselt number (Eq. 69 over
+    the cavity)."""
+    n, ref = TABLE1_MESH[Ra], table1()[Ra]
+    s = rt.Solver(2, (n, n), (0.0, 0.0), (1, 1, 2, 2), (0.5, -0.5, 0.0, 0.0), 1, Ra=Ra, Pr=0.71, Ma=0.1,
+                  precision=rt.FP64_PLAIN, seed=1, noise_amp=1e-6, residual_every=10_000)
+    for _ in range(400):  # at most 4M steps
+        s.step(10_000)
+        if max(s.residual()) < 1e-9:
+            break
+    res = s.residual()
+    L, chi = s.info.L, s.info.chi
+    xc = (np.arange(n) + 0.5) / n
+    u = s.grid(s.field(1))  # [row j (y), column i (x)]
+    v = s.grid(s.field(2))
+    h = n // 2
+    y_u, u_max = peak(xc, 0.5 * (u[:, h - 1] + u[:, h]) * L / chi)
+    x_v, v_max = peak(xc, 0.5 * (v[h - 1, :] + v[h, :]) * L / chi)
+    nu_a = s.nusselt()["volume"]
+    print(f"Ra {Ra:.0e} n {n}: residual {res}, u_max {u_max:.4f} at {y_u:.4f} (paper {ref['u_max']} at "
+          f"{ref['y']}), v_max {v_max:.4f} at {x_v:.4f} (paper {ref['v_max']} at {ref['x']}), Nu_a {nu_a:.4f} "
+          f"(paper {ref['Nu_a']})", flush=True)
+    # Observed: Nu_a within 2.4e-4, the maxima within 1.3e-3 and their
+    # positions within 1.6e-3 of the printed values (3-4 significant digits).
+    assert max(res) < 1e-9
+    assert abs(nu_a / ref["Nu_a"] - 1) < 1e-3
+    assert abs(u_max / ref["u_max"] - 1) < 3e-3 and abs(y_u - ref["y"]) < 5e-3
+    assert abs(v_max / ref["v_max"] - 1) < 3e-3 and abs(x_v - ref["x"]) < 5e-3
 
 
 def test_cubic_cavity_ra1e5_matches_table5():
