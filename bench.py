@@ -588,23 +588,6 @@ def stretch_for_first_cell(rt, n, first_over_L):
     return 0.5 * (lo + hi)
 
 
-def _peak(xs, ys):
-    """Maximum of sampled ys(xs) refined by the parabola through the largest
-    sample and its two neighbours: (value, position)."""
-    k = int(np.argmax(ys))
-    if k == 0 or k == len(ys) - 1:
-        return float(ys[k]), float(xs[k])
-    x0, x1, x2 = xs[k - 1], xs[k], xs[k + 1]
-    y0, y1, y2 = ys[k - 1], ys[k], ys[k + 1]
-    d0, d2 = (y0 - y1) / (x0 - x1), (y2 - y1) / (x2 - x1)
-    a = (d2 - d0) / (x2 - x0)            # curvature of the parabola
-    if a >= 0:
-        return float(y1), float(x1)
-    b = d0 - a * (x0 - x1)               # slope at x1
-    xm = x1 - b / (2 * a)
-    return float(y1 - b * b / (4 * a)), float(xm)
-
-
 def table23_quantities(rt, s, n, phi):
     """The quantities of Tables 2 and 3 from the absolute primitive fields:
     |psi/chi|_max and its position (psi = integral of u dy from the bottom
@@ -620,8 +603,8 @@ def table23_quantities(rt, s, n, phi):
     q = 0.5 * (rho[:, m - 1] * u[:, m - 1] * T[:, m - 1] + rho[:, m] * u[:, m] * T[:, m])
     q -= chi * (T[:, m] - T[:, m - 1]) / (xc[m] - xc[m - 1])
     nu_half = float(np.sum(q * dx) / chi)
-    um, uy = _peak(xc / L, 0.5 * (u[:, m - 1] + u[:, m]) * L / chi)
-    vm, vx = _peak(xc / L, 0.5 * (v[m - 1, :] + v[m, :]) * L / chi)
+    uy, um = _peak(xc / L, 0.5 * (u[:, m - 1] + u[:, m]) * L / chi)
+    vx, vm = _peak(xc / L, 0.5 * (v[m - 1, :] + v[m, :]) * L / chi)
     psi = np.abs(np.cumsum(u * dx[:, None], axis=0)) / chi  # at the top face of each cell
     j, i = np.unravel_index(int(np.argmax(psi)), psi.shape)
     return {"psi_max": float(psi[j, i]), "psi_x": float(xc[i] / L), "psi_y": float(x[j + 1] / L),

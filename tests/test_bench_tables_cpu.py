@@ -28,7 +28,7 @@ def test_stretch_gives_the_printed_first_cell(Ra):
 def test_peak_of_a_parabola_on_an_uneven_grid():
     xs = np.cumsum(np.r_[0.0, np.random.default_rng(5).uniform(0.05, 0.2, 15)])
     ys = 3.0 - 2.0 * (xs - 0.8137) ** 2
-    val, pos = bench._peak(xs, ys)
+    pos, val = bench._peak(xs, ys)
     assert abs(val - 3.0) < 1e-12 and abs(pos - 0.8137) < 1e-12
 
 
