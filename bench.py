@@ -296,8 +296,20 @@ def cube_bench(rt, torch, steps, warmup):
     return out
 
 
-TABLE5 = {1e5: {"u_max": 0.141, "z": 0.147, "w_max": 0.245, "x": 0.936, "Nu_m": 4.613, "Nu_o": 4.337},
+TABLE5 = {1e3: {"u_max": 0.132, "z": 0.185, "w_max": 0.133, "x": 0.825, "Nu_m": 1.089, "Nu_o": 1.071},
+          1e4: {"u_max": 0.198, "z": 0.175, "w_max": 0.220, "x": 0.885, "Nu_m": 2.251, "Nu_o": 2.055},
+          1e5: {"u_max": 0.141, "z": 0.147, "w_max": 0.245, "x": 0.936, "Nu_m": 4.613, "Nu_o": 4.337},
           1e6: {"u_max": 0.0812, "z": 0.138, "w_max": 0.257, "x": 0.963, "Nu_m": 8.882, "Nu_o": 8.643}}
+# Step cap per Ra: at Ra 1e3 and 1e4 the 80^3 cube is diffusion-dominated
+# (Delta t = 0.15 / chi is 0.10 and 0.32, one diffusion time L^2 / chi about
+# 1e6 steps), so it needs several times the steps of the convective cases.
+CUBE80_MAX_STEPS = {1e3: 4_000_000, 1e4: 3_000_000, 1e5: 800_000, 1e6: 800_000}
+# No plateau test before this many steps: from rest, the hot-wall Nusselt
+# number first falls (conduction) and then rises (convection), and passes a
+# minimum where its change per chunk vanishes; at Ra 1e3 and 1e4 that minimum
+# comes long before the steady state, which takes about two diffusion times.
+CUBE80_MIN_STEPS = {1e3: 2_000_000, 1e4: 2_000_000, 1e5: 0, 1e6: 0}
+CUBE80_CASES = tuple(sorted(TABLE5))  # --ra selects one
 
 
 def _peak(xc, f):
@@ -315,9 +327,9 @@ def _peak(xc, f):
     return float(xm), float(a * xm * xm + b * xm + c)
 
 
-def cube_table5_bench(rt, torch, steps, warmup, n=80, chunk=20_000, max_steps=800_000, tol=2e-5):
+def cube_table5_bench(rt, torch, steps, warmup, n=80, chunk=20_000, tol=2e-5):
     """The 3D cubic cavity of the paper's Sec. 4.4 on its 80^3 tanh mesh (phi =
-    1.8), Ra = 1e5 and 1e6, FP32 deviation storage, run until the hot-wall
+    1.8), Ra = 1e3 ... 1e6, FP32 deviation storage, run until the hot-wall
     Nusselt number changes by less than tol (relative) over a chunk.  Reported
     against the printed 'Present' values: u_max / V_c on the vertical centre
     line (x = y = L/2) and its height, w_max / V_c on the horizontal centre
@@ -328,7 +340,8 @@ def cube_table5_bench(rt, torch, steps, warmup, n=80, chunk=20_000, max_steps=80
     xc = 0.5 * (x[1:] + x[:-1]) / L
     w_first = (x[1] - x[0])
     h = n // 2
-    for Ra in (1e5, 1e6):
+    for Ra in CUBE80_CASES:
+        max_steps, min_steps = CUBE80_MAX_STEPS[Ra], CUBE80_MIN_STEPS[Ra]
         s = rt.Solver(3, (n, n, n), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=Ra,
                       Pr=0.71, Ma=MA, precision=rt.FP32_DEV, seed=1, noise_amp=1e-6)
         t0 = time.perf_counter()
@@ -337,7 +350,10 @@ def cube_table5_bench(rt, torch, steps, warmup, n=80, chunk=20_000, max_steps=80
             s.step(chunk)
             done += chunk
             nu = s.nusselt()
-            if prev is not None and abs(nu["hot_avg"] - prev) < tol * abs(nu["hot_avg"]):
+            if done % (10 * chunk) == 0:
+                print(f"# Ra {Ra:g}: {done} steps, Nu hot {nu['hot_avg']:.5f}, {time.perf_counter() - t0:.0f} s",
+                      flush=True)
+            if done > min_steps and prev is not None and abs(nu["hot_avg"] - prev) < tol * abs(nu["hot_avg"]):
                 break
             prev = nu["hot_avg"]
         el = time.perf_counter() - t0
@@ -885,7 +901,7 @@ def main():
                                                            "dhc_highra"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
                          "tanh cube, Ra=1e6; steady256: the 256^2 cavity to steady state, FP32 vs FP64 Nusselt; "
-                         "cube80: the 80^3 cubic cavity at Ra 1e5 and 1e6 to steady state against Table 5; "
+                         "cube80: the 80^3 cubic cavity at Ra 1e3 ... 1e6 to steady state against Table 5; "
                          "hill: the Gaussian-hill convergence study of Sec. 4.1; methods: RTLBFS vs TLBFS step cost; "
                          "stability: the stability maps of Figs. 4-5 as batched runs; cylinder: the body-fitted "
                          "step on the 450x300 O-mesh of Sec. 4.3; cylinder_table4: Table 4, Gr 0..1600; "
@@ -894,14 +910,20 @@ def main():
                          "(Ra 1e7 on 300^2, Ra 1e8 on 400^2) to steady state or --budget-s")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
-    ap.add_argument("--ra", type=float, default=None, help="dhc_highra: run only this Rayleigh number (1e7 or 1e8)")
+    ap.add_argument("--ra", type=float, default=None,
+                    help="dhc_highra (1e7 or 1e8) and cube80 (1e3 ... 1e6): run only this Rayleigh number")
     ap.add_argument("--budget-s", type=float, default=None, help="dhc_highra: wall-clock seconds per case")
     args = ap.parse_args()
-    global HIGHRA_CASES, HIGHRA_BUDGET_S
+    global HIGHRA_CASES, HIGHRA_BUDGET_S, CUBE80_CASES
     if args.ra is not None:
-        if args.ra not in TABLES_2_3:
-            ap.error("--ra must be 1e7 or 1e8")
-        HIGHRA_CASES = (args.ra,)
+        if args.workload == "cube80":
+            if args.ra not in TABLE5:
+                ap.error("--ra must be 1e3, 1e4, 1e5 or 1e6 for cube80")
+            CUBE80_CASES = (args.ra,)
+        else:
+            if args.ra not in TABLES_2_3:
+                ap.error("--ra must be 1e7 or 1e8")
+            HIGHRA_CASES = (args.ra,)
     if args.budget_s is not None:
         HIGHRA_BUDGET_S = args.budget_s
     if args.gpus != 1:
