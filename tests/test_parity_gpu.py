@@ -97,6 +97,18 @@ def test_fp64_c1_parity_1000_steps_and_diagnostics():
     assert abs(ig["mass_dev"] - io["mass_dev"]) <= 1e-12 * io["volume"]
 
 
+def test_fp64_c1_parity_20000_steps():
+    """The small configuration over a long horizon: the 64^2 uniform cavity at
+    Ra = 1e3 for 20,000 steps (t* = 62, most of the way to steady state),
+    fields within 1e-12 of the oracle.  The oracle needs about a minute."""
+    s, o = make_pair(2, (64, 64), (0.0, 0.0), **DHC2, Ra=1e3, noise=1e-6)
+    s.step(20000)
+    o.step(20000)
+    rel = field_rel(s, o, 2)
+    print("64^2, 20000 steps: rel", rel, flush=True)
+    assert max(rel) <= FP64_TOL, rel
+
+
 def test_fp64_periodic_rayleigh_benard_parity():
     """Rayleigh-Benard box periodic in x (wrapped halos, ragged periodic
     tiles): 400 steps."""
@@ -280,6 +292,18 @@ def test_fp64_3d_cavity_parity(prec):
     s.step(120)
     o.step(120)
     rel = field_rel(s, o, 3)
+    assert max(rel) <= FP64_TOL, rel
+
+
+def test_fp64_3d_48cube_tanh_parity_200_steps():
+    """A 48^3 tanh (phi = 1.8) cubic cavity at Ra = 1e5, 200 steps: six 8x4x4
+    tiles per x row, twelve in y and z, fields within 1e-12.  The oracle
+    needs about a minute."""
+    s, o = make_pair(3, (48, 48, 48), (1.8, 1.8, 1.8), **DHC3, Ra=1e5, noise=1e-3)
+    s.step(200)
+    o.step(200)
+    rel = field_rel(s, o, 3)
+    print("48^3 tanh, 200 steps: rel", rel, flush=True)
     assert max(rel) <= FP64_TOL, rel
 
 
