@@ -162,7 +162,8 @@ int rtlbfs_opts_init(rtlbfs_opts *opts);
 int rtlbfs_mesh_nodes(int n, double stretch, double *host_x, double *L);
 
 /* Device workspace needed for this mesh and precision (bytes, 256-aligned);
- * 0 when the arguments are invalid. */
+ * 0 when the arguments are invalid or the mesh exceeds the size limit of
+ * rtlbfs_create. */
 size_t rtlbfs_workspace_bytes(const rtlbfs_mesh *mesh, const rtlbfs_opts *opts);
 
 /* Create a solver for one domain.
@@ -175,7 +176,10 @@ size_t rtlbfs_workspace_bytes(const rtlbfs_mesh *mesh, const rtlbfs_opts *opts);
  *   out: receives the handle.
  * Uploads the seeded initial state (synchronising).  Errors: EINVAL
  * (validation: Ra, Pr > 0, 0 < Ma <= 0.3, n >= 4, paired periodic sides,
- * uniform mesh on periodic axes, gravity_axis < dim), ENOMEM, EDEVICE. */
+ * uniform mesh on periodic axes, gravity_axis < dim), ENOMEM, EDEVICE.
+ * Size limit: at most 2^20 cells per axis, and every step launch within one
+ * dispatch (launch-shape blocks x threads at most 2^32 - 1, about 7e8 cells
+ * for a square 2D mesh); a larger mesh is EINVAL. */
 int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, const rtlbfs_bc *bc,
                   const rtlbfs_opts *opts, void *hip_stream, void *workspace, size_t ws_bytes,
                   rtlbfs_t *out);
@@ -263,7 +267,8 @@ typedef struct {
     double T_inf;    /* far-field absolute temperature (also the initial temperature) */
 } rtlbfs_curv_bc;
 
-/* Device workspace for a body-fitted mesh (bytes); 0 for invalid arguments. */
+/* Device workspace for a body-fitted mesh (bytes); 0 for invalid arguments
+ * or a mesh beyond the size limit of rtlbfs_create. */
 size_t rtlbfs_curv_workspace_bytes(const rtlbfs_curv_mesh *mesh, const rtlbfs_opts *opts);
 
 /* Create a solver on a body-fitted mesh.  nu, chi, beta_g are given directly
@@ -356,7 +361,10 @@ int rtlbfs_curv3_cells(rtlbfs_t h, double *host_cx, double *host_cy, double *hos
  * covers the tiles of every member, replayed from a captured HIP graph.
  * meshes, Ra, Pr and bcs are arrays of `count`; each member has its own
  * lattice units, Eq. 63 parameters and Delta-t (the dtl/dt defaults apply per
- * member).  Precision must be the same for all (opts->precision). */
+ * member).  Precision must be the same for all (opts->precision).  The step
+ * launch covers every member's tiles and must fit one dispatch (blocks x
+ * threads at most 2^32 - 1, about 1.7e9 cells in total); a larger batch is
+ * EINVAL (workspace bytes 0). */
 size_t rtlbfs_batch_workspace_bytes(int count, const rtlbfs_mesh *meshes, const rtlbfs_opts *opts);
 
 int rtlbfs_batch_create(int count, const rtlbfs_mesh *meshes, const double *Ra, const double *Pr, double Ma,

@@ -90,7 +90,30 @@ struct Tile2 {
 constexpr Tile2 kTiles2[] = {{32, 8, 1, 0},  {16, 16, 1, 1}, {64, 4, 1, 2}, {16, 8, 1, 3}, {8, 8, 1, 4},
                              {16, 16, 2, 1}, {32, 8, 2, 0},  {16, 8, 2, 3}, {8, 8, 2, 4}};
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
+// Threads per block of each 2D launch shape, in kTiles2 order (the shapes
+// launch_step instantiates).
+constexpr int kTiles2Threads[] = {tile2_threads<32, 8, 1>(),  tile2_threads<16, 16, 1>(), tile2_threads<64, 4, 1>(),
+                                  tile2_threads<16, 8, 1>(),  tile2_threads<8, 8, 1>(),   tile2_threads<16, 16, 2>(),
+                                  tile2_threads<32, 8, 2>(),  tile2_threads<16, 8, 2>(),  tile2_threads<8, 8, 2>()};
+static_assert(sizeof(kTiles2Threads) / sizeof(kTiles2Threads[0]) == kNumTiles2, "one thread count per shape");
 constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per face)
+// A dispatch's grid holds at most 2^32 - 1 work-items (blocks x threads).
+constexpr int64_t kMaxWorkItems = 0xFFFFFFFFll;
+
+// Every step launch the autotuner may pick for this Cartesian mesh fits one
+// dispatch (meshes within the per-axis limit of 2^20 cells).
+bool step_launches_fit(const rtlbfs_mesh &m) {
+    if (m.dim == 2) {
+        for (int t = 0; t < kNumTiles2; ++t) {
+            const int64_t b = (int64_t)((m.n[0] + kTiles2[t].tx - 1) / kTiles2[t].tx) *
+                              ((m.n[1] + kTiles2[t].ty - 1) / kTiles2[t].ty);
+            if (b * kTiles2Threads[t] > kMaxWorkItems) return false;
+        }
+        return true;
+    }
+    const int64_t b = (int64_t)((m.n[0] + kTX3 - 1) / kTX3) * ((m.n[1] + kTY3 - 1) / kTY3) * ((m.n[2] + kTZ3 - 1) / kTZ3);
+    return b * tile3_threads<kTX3, kTY3, kTZ3>() <= kMaxWorkItems;
+}
 constexpr int kRedBlocks = 512;                // blocks of the diagnostics kernels
 
 struct Layout {
@@ -295,6 +318,21 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
 int curv_blocks(const rtlbfs_mesh &m, int tile) {
     const TileC t = kTilesC[tile];
     return ((m.n[0] + t.tx - 1) / t.tx) * ((m.n[1] + t.ty - 1) / t.ty);
+}
+
+// Threads per block of each body-fitted 2D launch shape, in kTilesC order.
+constexpr int kTilesCThreads[] = {curv_threads<16, 16>(), curv_threads<16, 8>(), curv_threads<32, 8>(),
+                                  curv_threads<8, 8>()};
+static_assert(sizeof(kTilesCThreads) / sizeof(kTilesCThreads[0]) == kNumTilesC, "one thread count per shape");
+
+// Every launch shape of the body-fitted 2D step fits one dispatch for an
+// ni x nj mesh (each axis within 2^20 cells).
+bool curv_launches_fit(int ni, int nj) {
+    for (int t = 0; t < kNumTilesC; ++t) {
+        const int64_t b = (int64_t)((ni + kTilesC[t].tx - 1) / kTilesC[t].tx) * ((nj + kTilesC[t].ty - 1) / kTilesC[t].ty);
+        if (b * kTilesCThreads[t] > kMaxWorkItems) return false;
+    }
+    return true;
 }
 
 // Blocks of one step launch of the handle (rows of residual partials).
@@ -658,7 +696,8 @@ int rtlbfs_mesh_nodes(int n, double stretch, double *host_x, double *L) { return
 size_t rtlbfs_workspace_bytes(const rtlbfs_mesh *mesh, const rtlbfs_opts *opts) {
     if (!mesh || (mesh->dim != 2 && mesh->dim != 3)) return 0;
     for (int a = 0; a < mesh->dim; ++a)
-        if (mesh->n[a] < 4) return 0;
+        if (mesh->n[a] < 4 || mesh->n[a] > (1 << 20)) return 0;
+    if (!step_launches_fit(*mesh)) return 0;
     rtlbfs_opts o;
     if (opts) o = *opts;
     else rtlbfs_opts_init(&o);
@@ -679,6 +718,10 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
     if (rc != RTLBFS_OK) {
         g_create_err = why;
         return rc;
+    }
+    if (!step_launches_fit(P.mesh)) {
+        g_create_err = "mesh too large: a step launch would exceed 2^32 - 1 work-items";
+        return RTLBFS_EINVAL;
     }
     rtlbfs_t h = new (std::nothrow) rtlbfs_handle();
     if (!h) return RTLBFS_ENOMEM;
@@ -975,6 +1018,7 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
 
 size_t rtlbfs_curv_workspace_bytes(const rtlbfs_curv_mesh *mesh, const rtlbfs_opts *opts) {
     if (!mesh || mesh->n[0] < 4 || mesh->n[1] < 4 || mesh->n[0] > (1 << 20) || mesh->n[1] > (1 << 20)) return 0;
+    if (!curv_launches_fit(mesh->n[0], mesh->n[1])) return 0;
     rtlbfs_opts o;
     if (opts) o = *opts;
     else rtlbfs_opts_init(&o);
@@ -1006,6 +1050,10 @@ int rtlbfs_curv_create(const rtlbfs_curv_mesh *mesh, double nu, double chi, doub
     if (rc != RTLBFS_OK) {
         g_create_err = why;
         return rc;
+    }
+    if (!curv_launches_fit(mesh->n[0], mesh->n[1])) {
+        g_create_err = "mesh too large: a step launch would exceed 2^32 - 1 work-items";
+        return RTLBFS_EINVAL;
     }
     Problem P;
     P.mesh.dim = 2;

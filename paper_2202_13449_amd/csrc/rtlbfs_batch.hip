@@ -129,6 +129,19 @@ struct BatchLayout {
 
 int tiles_of(const rtlbfs_mesh &m) { return ((m.n[0] + kBTX - 1) / kBTX) * ((m.n[1] + kBTY - 1) / kBTY); }
 
+// The batch step launch covers every member's tiles; a dispatch's grid holds
+// at most 2^32 - 1 work-items (blocks x threads).
+bool batch_launch_fits(int count, const rtlbfs_mesh *meshes) {
+    int64_t items = 0;
+    for (int m = 0; m < count; ++m) {
+        if (meshes[m].n[0] > (1 << 20) || meshes[m].n[1] > (1 << 20)) return false;
+        items += (int64_t)((meshes[m].n[0] + kBTX - 1) / kBTX) * ((meshes[m].n[1] + kBTY - 1) / kBTY) *
+                 tile2_threads<kBTX, kBTY>();
+        if (items > 0xFFFFFFFFll) return false;
+    }
+    return true;
+}
+
 BatchLayout batch_layout(int count, const rtlbfs_mesh *meshes, int precision) {
     BatchLayout l{};
     l.nwork = 0;
@@ -265,6 +278,7 @@ size_t rtlbfs_batch_workspace_bytes(int count, const rtlbfs_mesh *meshes, const 
     if (count <= 0 || !meshes) return 0;
     for (int m = 0; m < count; ++m)
         if (meshes[m].dim != 2 || meshes[m].n[0] < 4 || meshes[m].n[1] < 4) return 0;
+    if (!batch_launch_fits(count, meshes)) return 0;
     rtlbfs_opts o;
     if (opts) o = *opts;
     else rtlbfs_opts_init(&o);
@@ -285,6 +299,9 @@ int rtlbfs_batch_create(int count, const rtlbfs_mesh *meshes, const double *Ra, 
     if (o.mass_fix_every == 0) o.mass_fix_every = 1000;
     for (int m = 0; m < count; ++m)
         if (meshes[m].dim != 2) return RTLBFS_EUNSUPPORTED;  // batched members are 2D domains
+    for (int m = 0; m < count; ++m)
+        if (meshes[m].n[0] < 4 || meshes[m].n[1] < 4) return RTLBFS_EINVAL;
+    if (!batch_launch_fits(count, meshes)) return RTLBFS_EINVAL;  // the step launch would exceed 2^32 - 1 work-items
     rtlbfs_batch_t h = new (std::nothrow) rtlbfs_batch_handle();
     if (!h) return RTLBFS_ENOMEM;
     h->count = count;

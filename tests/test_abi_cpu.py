@@ -279,3 +279,41 @@ def test_curv3_create_rejects_invalid_problems_before_touching_the_device(case):
         X, Y, Z = X[:, :, :2], Y[:, :, :2], Z[:, :, :2]  # one radial cell between two walls
     rc, h = _c3_create(X, Y, Z, b, **kw)
     assert rc == rt.EINVAL and not h.value, rt.load_library().rtlbfs_last_error(None)
+
+
+def test_meshes_beyond_one_dispatch_are_rejected_before_touching_the_device():
+    """Maximum sizes.  Every axis may hold 2^20 cells, but a step launch must
+    fit one dispatch: blocks x threads of every launch shape at most
+    2^32 - 1.  A mesh past that has no workspace size and is EINVAL at
+    create, for the single-domain, batched and body-fitted entry points;
+    meshes just inside are accepted."""
+    lib = rt.load_library()
+    o = rt.make_opts(precision=rt.FP32_DEV)
+    big2 = rt.make_mesh(2, (1 << 20, 8192))        # 8.6e9 cells: the 8 x 8 two-step shape needs 5e10 work-items
+    assert lib.rtlbfs_workspace_bytes(C.byref(big2), C.byref(o)) == 0
+    bc = rt.make_bc((1, 1, 2, 2), (0.5, -0.5, 0, 0), 1)
+    rc, h = _create(big2, bc, opts=o)
+    assert rc == rt.EINVAL and not h.value
+    assert b"too large" in lib.rtlbfs_last_error(None)
+    ok2 = rt.make_mesh(2, (4096, 4096))
+    assert lib.rtlbfs_workspace_bytes(C.byref(ok2), C.byref(o)) > 0
+    big3 = rt.make_mesh(3, (1024, 1024, 1024))     # 8.4e6 tiles of 512 threads: 4.3e9 work-items
+    ok3 = rt.make_mesh(3, (1000, 1000, 1000))      # 7.8e6 tiles: 4.0e9
+    assert lib.rtlbfs_workspace_bytes(C.byref(big3), C.byref(o)) == 0
+    assert lib.rtlbfs_workspace_bytes(C.byref(ok3), C.byref(o)) > 0
+    too_long = rt.make_mesh(2, ((1 << 20) + 1, 4))
+    assert lib.rtlbfs_workspace_bytes(C.byref(too_long), C.byref(o)) == 0
+    # batch: two members of 2^20 x 4096 need 2.1e10 work-items together
+    meshes = (rtb.Mesh * 2)(rt.make_mesh(2, (1 << 20, 4096)), rt.make_mesh(2, (1 << 20, 4096)))
+    assert lib.rtlbfs_batch_workspace_bytes(2, meshes, C.byref(o)) == 0
+    bcs = (rtb.BC * 2)(bc, bc)
+    Ra, Pr = (C.c_double * 2)(1e3, 1e3), (C.c_double * 2)(0.71, 0.71)
+    hb = C.c_void_p()
+    assert lib.rtlbfs_batch_create(2, meshes, Ra, Pr, 0.1, bcs, C.byref(o), None, None, 0, C.byref(hb)) == rt.EINVAL
+    assert not hb.value
+    small = (rtb.Mesh * 2)(rt.make_mesh(2, (64, 64)), rt.make_mesh(2, (128, 96)))
+    assert lib.rtlbfs_batch_workspace_bytes(2, small, C.byref(o)) > 0
+    # body-fitted 2D
+    cm = rtb.CurvMesh()
+    cm.n[:] = [1 << 20, 8192]
+    assert lib.rtlbfs_curv_workspace_bytes(C.byref(cm), C.byref(o)) == 0
