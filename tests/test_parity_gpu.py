@@ -238,6 +238,31 @@ def test_minimum_mesh_and_single_tile():
     assert max(field_rel(s, o, 2)) <= FP64_TOL
 
 
+def test_empty_and_invalid_calls_on_a_live_handle():
+    """Degenerate calls on a live handle: zero steps leave the state bit for
+    bit; a negative step count, a short output buffer and a field index out
+    of range are EINVAL and change nothing; the handle keeps working, and a
+    one-step call after them matches the oracle (one step in a two-step
+    shape runs the one-step launch of the same tile)."""
+    import ctypes as C
+
+    s, o = make_pair(2, (20, 12), (1.2, 0.0), **DHC2, Ra=1e4, tile=6)
+    s.step(7)
+    o.step(7)
+    before = [s.stored(f).copy() for f in range(4)]
+    s.step(0)
+    lib, h = s._lib, s._h
+    assert lib.rtlbfs_step(h, -1) == rt.EINVAL
+    buf = np.zeros(s.cells)
+    assert lib.rtlbfs_get_field(h, 0, buf.ctypes.data_as(C.POINTER(C.c_double)), s.cells - 1) == rt.EINVAL
+    assert lib.rtlbfs_get_field(h, 4, buf.ctypes.data_as(C.POINTER(C.c_double)), s.cells) == rt.EINVAL
+    for f in range(4):
+        assert np.array_equal(s.stored(f), before[f])
+    s.step(1)
+    o.step(1)
+    assert max(field_rel(s, o, 2)) <= FP64_TOL
+
+
 @pytest.mark.parametrize("tile", [0, 6])
 def test_c2_full_size_prefix_fp64(tile):
     """256^2 tanh (phi = 1.5) cavity at Ra = 1e6, the benchmarked
