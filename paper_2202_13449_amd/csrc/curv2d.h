@@ -149,6 +149,8 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
     const int nx = d.n[0], ny = d.n[1];
     const int64_t N = d.fstride;
     const bool px = d.periodic[0], py = d.periodic[1];
+    // a periodic axis at least as long as the tile plus both 2-cell halos wraps by selects
+    const bool nearx = nx >= TX + 4, neary = ny >= TY + 4;
     const Phys<R> &ph = make_phys<R>(d);
     const R *__restrict__ fi = (const R *)g.fi;
     const R *__restrict__ fj = (const R *)g.fj;
@@ -162,8 +164,8 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
     if (tid < PF) {
         const int li = tid % PX, lj = tid / PX;
         int gi = i0 - 2 + li, gj = j0 - 2 + lj;
-        if (px) gi = wrap(gi, nx);
-        if (py) gj = wrap(gj, ny);
+        if (px) gi = wrap_axis(gi, nx, nearx);
+        if (py) gj = wrap_axis(gj, ny, neary);
         if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
             const int64_t c = (int64_t)gj * nx + gi;
             const R r = Uin[c], mx = Uin[N + c], my = Uin[2 * N + c], e = Uin[3 * N + c];
@@ -195,8 +197,8 @@ __device__ __forceinline__ void tile_step_curv(const Domain &d, const CurvGeo &g
     if (tid < GF) {
         const int li = tid % GX, lj = tid / GX;
         int gi = i0 - 1 + li, gj = j0 - 1 + lj;
-        if (px) gi = wrap(gi, nx);
-        if (py) gj = wrap(gj, ny);
+        if (px) gi = wrap_axis(gi, nx, nearx);
+        if (py) gj = wrap_axis(gj, ny, neary);
         if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
             const int ci = li + 1, cj = lj + 1;  // position in sp
             R P[4];

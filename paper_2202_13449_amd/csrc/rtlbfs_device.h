@@ -464,4 +464,18 @@ __device__ inline int wrap(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
+// wrap(i, n) for -n <= i < 2n, by two selects instead of an integer
+// remainder.  A tile kernel takes it on a periodic axis of n cells when the
+// tile plus both halos is no wider than n: its halo and ragged-tile
+// positions (tile start below n, halo depth h) then lie in [-h, n + tile + h).
+__device__ inline int wrap_near(int i, int n) {
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// The index wrap of one periodic axis: near (a scalar, the same for the whole
+// block) selects wrap_near.
+__device__ inline int wrap_axis(int i, int n, bool near) {
+    return near ? wrap_near(i, n) : wrap(i, n);
+}
+
 }  // namespace rtlbfs

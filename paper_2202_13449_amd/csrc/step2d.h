@@ -115,7 +115,8 @@ struct SubView {
 template <typename R, bool DEV, bool TL, int UX, int UY, bool LAST, bool RES, int NT, int LAYOUT>
 __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, const SubView<R> &v, R *sp_next,
                                            const R *swT, const int *swIso, R *__restrict__ Uout,
-                                           double *__restrict__ part, double *sred, uint32_t step_key) {
+                                           double *__restrict__ part, double *sred, uint32_t step_key, bool nearx,
+                                           bool neary) {
     constexpr int PX = UX + 4, PY = UY + 4;  // primitives with a 2-cell halo
     constexpr int GX = UX + 2, GY = UY + 2;  // gradients with a 1-cell halo
     constexpr int NFX = (UX + 1) * UY;
@@ -138,8 +139,8 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
     if (tid < GX * GY) {
         const int li = tid % GX, lj = tid / GX;
         int gi = ux0 - 1 + li, gj = uy0 - 1 + lj;
-        if (px) gi = wrap(gi, nx);
-        if (py) gj = wrap(gj, ny);
+        if (px) gi = wrap_axis(gi, nx, nearx);
+        if (py) gj = wrap_axis(gj, ny, neary);
         if (gi >= 0 && gi < nx && gj >= 0 && gj < ny) {
             const int ci = li + 1, cj = lj + 1;  // position in sp
             const bool wall_w = !px && gi == 0, wall_e = !px && gi == nx - 1;
@@ -282,8 +283,8 @@ __device__ __forceinline__ void substep_2d(const Domain &d, int ux0, int uy0, co
         if (LAST) {
             ok = gi < nx && gj < ny;
         } else {
-            if (px) gi = wrap(gi, nx);
-            if (py) gj = wrap(gj, ny);
+            if (px) gi = wrap_axis(gi, nx, nearx);
+            if (py) gj = wrap_axis(gj, ny, neary);
             ok = gi >= 0 && gi < nx && gj >= 0 && gj < ny;
         }
         if (ok) {
@@ -379,6 +380,8 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     const int nx = d.n[0], ny = d.n[1];
     const int64_t N = d.fstride;
     const bool px = d.periodic[0], py = d.periodic[1];
+    // a periodic axis at least as long as the tile plus both halos wraps by selects
+    const bool nearx = nx >= TX + 2 * H, neary = ny >= TY + 2 * H;
     const R *__restrict__ geox = (const R *)d.geo[0];
     const R *__restrict__ geoy = (const R *)d.geo[1];
     const int tid = threadIdx.x;
@@ -388,8 +391,8 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     {
         const int li = tid % LX, lj = tid / LX;
         int gi = i0 - H + li, gj = j0 - H + lj;
-        if (px) gi = wrap(gi, nx);
-        if (py) gj = wrap(gj, ny);
+        if (px) gi = wrap_axis(gi, nx, nearx);
+        if (py) gj = wrap_axis(gj, ny, neary);
         const bool ld = tid < LX * LY && gi >= 0 && gi < nx && gj >= 0 && gj < ny;  // outside a wall: never read
         R r = 0, mx = 0, my = 0, e = 0;
         if (ld) {
@@ -403,7 +406,7 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
         const int gl = isx ? tid : tid - LX;
         const int gn = isx ? nx : ny;
         int g = (isx ? i0 : j0) - H + gl;
-        if (isx ? px : py) g = wrap(g, gn);
+        if (isx ? px : py) g = wrap_axis(g, gn, nearx && neary);  // one choice for the block
         const bool lg = tid < LX + LY && g >= 0 && g < gn;
         R gv[kGeoFields];
         if (lg) {
@@ -450,17 +453,17 @@ __device__ __forceinline__ void tile_step_2d(const Domain &d, int i0, int j0, co
     if constexpr (NSUB == 1) {
         const SubView<R> v{spA, sg, sf, sc, 0, TX, SCF, sgx, sgy, LX, LY, 0, 0};
         substep_2d<R, DEV, TL, TX, TY, true, RES, NT, LB>(d, i0, j0, v, nullptr, swT, swIso, Uout, part, sred,
-                                                          step_key);
+                                                          step_key, nearx, neary);
     } else {
         const SubView<R> va{spA, sg, sf, sc, 0, U0X, SCF, sgx, sgy, LX, LY, 0, 0};
         substep_2d<R, DEV, TL, U0X, U0Y, false, false, NT, LA>(d, i0 - 2, j0 - 2, va, spB, swT, swIso, nullptr,
-                                                               nullptr, sred, step_key);
+                                                               nullptr, sred, step_key, nearx, neary);
         __syncthreads();
         // second sub-step: primitives from spB, old state inside sc at (2, 2),
         // geometry shifted by the two cells the region shrank by
         const SubView<R> vb{spB, sg, sf, sc, 2 * U0X + 2, U0X, SCF, sgx, sgy, LX, LY, 2, 2};
         substep_2d<R, DEV, TL, TX, TY, true, RES, NT, LB>(d, i0, j0, vb, nullptr, swT, swIso, Uout, part, sred,
-                                                          step_key + 1u);
+                                                          step_key + 1u, nearx, neary);
     }
 }
 

@@ -59,6 +59,8 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     const int64_t N = d.fstride;
     const Phys<R> &ph = make_phys<R>(d);
     const int tid = threadIdx.x;
+    // a periodic axis at least as long as the tile plus both 2-cell halos wraps by selects
+    const bool nearx = nx >= TX + 4, neary = ny >= TY + 4, nearz = nz >= TZ + 4;
 
     // Phase 1: state of the tile and halo (NIT passes, all loads issued
     // before the first use), then the geometry of the three halo lines.
@@ -70,9 +72,9 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
             const int q = tid + it * NT;
             const int lx = q % TT::PX, ly = (q / TT::PX) % TT::PY, lz = q / (TT::PX * TT::PY);
             int gx = i0 - 2 + lx, gy = j0 - 2 + ly, gz = k0 - 2 + lz;
-            if (px) gx = wrap(gx, nx);
-            if (py) gy = wrap(gy, ny);
-            if (pz) gz = wrap(gz, nz);
+            if (px) gx = wrap_axis(gx, nx, nearx);
+            if (py) gy = wrap_axis(gy, ny, neary);
+            if (pz) gz = wrap_axis(gz, nz, nearz);
             ld[it] = q < TT::NP && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
             if (ld[it]) {
                 const int64_t c = ((int64_t)gz * ny + gy) * nx + gx;
@@ -84,7 +86,7 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
         const int gl = tid - (ga == 0 ? 0 : (ga == 1 ? off1 : off2));
         const int gn = ga == 0 ? nx : (ga == 1 ? ny : nz);
         int g = (ga == 0 ? i0 : (ga == 1 ? j0 : k0)) - 2 + gl;
-        if (ga == 0 ? px : (ga == 1 ? py : pz)) g = wrap(g, gn);
+        if (ga == 0 ? px : (ga == 1 ? py : pz)) g = wrap_axis(g, gn, nearx && neary && nearz);  // one choice
         const bool lg = tid < TT::GEO && g >= 0 && g < gn;
         R gv[kGeoFields];
         if (lg) {
@@ -132,9 +134,9 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
     if (tid < TT::NG) {
         const int lx = tid % TT::GX, ly = (tid / TT::GX) % TT::GY, lz = tid / (TT::GX * TT::GY);
         int gx = i0 - 1 + lx, gy = j0 - 1 + ly, gz = k0 - 1 + lz;
-        if (px) gx = wrap(gx, nx);
-        if (py) gy = wrap(gy, ny);
-        if (pz) gz = wrap(gz, nz);
+        if (px) gx = wrap_axis(gx, nx, nearx);
+        if (py) gy = wrap_axis(gy, ny, neary);
+        if (pz) gz = wrap_axis(gz, nz, nearz);
         if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
             const int pc = TT::pidx(lx + 1, ly + 1, lz + 1);
             const int gq[3] = {gx, gy, gz};
