@@ -263,6 +263,58 @@ def test_empty_and_invalid_calls_on_a_live_handle():
     assert max(field_rel(s, o, 2)) <= FP64_TOL
 
 
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP32_DEV])
+def test_two_runs_are_bitwise_identical(prec):
+    """Determinism: two handles of the same problem, stepped alike, hold the
+    same stored state bit for bit, and the FP64 diagnostics (Eq. 65 residual,
+    Nusselt numbers, integrals) are equal; the reductions run in a fixed
+    order and the stochastic rounding is keyed by (cell, step, field)."""
+    args = (2, (40, 28), (1.3, 1.3), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"])
+    a = rt.Solver(*args, Ra=1e5, precision=prec, seed=3, noise_amp=1e-3, residual_every=50)
+    b = rt.Solver(*args, Ra=1e5, precision=prec, seed=3, noise_amp=1e-3, residual_every=50)
+    a.step(300)
+    b.step(130)
+    b.step(170)
+    for f in range(4):
+        assert np.array_equal(a.stored(f), b.stored(f)), f
+    assert a.residual() == b.residual()
+    assert a.nusselt() == b.nusselt()
+    assert a.integrals() == b.integrals()
+
+
+def test_divergence_is_reported_and_clears():
+    """Failure detection, forced from the host: a state moving at Mach 0.69
+    (above the default guard of 0.5), and then one with a NaN temperature,
+    makes the synchronising call after the next residual step return
+    EDIVERGED without stopping the handle; a valid state clears the flag at
+    the following residual step."""
+    s = rt.Solver(2, (32, 32), (0.0, 0.0), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"], Ra=1e4, residual_every=1)
+    n = s.cells
+    s.step(3)
+    s.sync()
+    u = np.zeros(2 * n)
+    u[:n] = 0.4  # |u| / c_s = 0.69
+    s.set_state(np.ones(n), u, np.full(n, 0.5))
+    s.step(1)
+    with pytest.raises(rt.RtlbfsError) as e:
+        s.sync()
+    assert e.value.code == rt.EDIVERGED
+    s.set_state(np.ones(n), np.zeros(2 * n), np.full(n, 0.5))
+    s.step(1)
+    s.sync()
+    T = np.full(n, 0.5)
+    T[n // 3] = np.nan
+    s.set_state(np.ones(n), np.zeros(2 * n), T)
+    s.step(1)
+    with pytest.raises(rt.RtlbfsError) as e:
+        s.sync()
+    assert e.value.code == rt.EDIVERGED
+    s.set_state(np.ones(n), np.zeros(2 * n), np.full(n, 0.5))
+    s.step(2)
+    s.sync()
+    assert np.isfinite(s.field(3)).all()
+
+
 @pytest.mark.parametrize("tile", [0, 6])
 def test_c2_full_size_prefix_fp64(tile):
     """256^2 tanh (phi = 1.5) cavity at Ra = 1e6, the benchmarked
