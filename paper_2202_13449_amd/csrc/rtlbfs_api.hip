@@ -96,7 +96,10 @@ constexpr int kTiles2Threads[] = {tile2_threads<32, 8, 1>(),  tile2_threads<16, 
                                   tile2_threads<16, 8, 1>(),  tile2_threads<8, 8, 1>(),   tile2_threads<16, 16, 2>(),
                                   tile2_threads<32, 8, 2>(),  tile2_threads<16, 8, 2>(),  tile2_threads<8, 8, 2>()};
 static_assert(sizeof(kTiles2Threads) / sizeof(kTiles2Threads[0]) == kNumTiles2, "one thread count per shape");
-constexpr int kTX3 = 8, kTY3 = 4, kTZ3 = 4;    // 3D tile (one thread per face)
+// 3D tile, one thread per face: 240 faces on four wavefronts.  In FP32 its
+// ~30 KB of LDS and 96 VGPRs leave room for five blocks (20 wavefronts) per
+// CU, where the 8 x 4 x 4 tile's eight wavefronts fit twice (16).
+constexpr int kTX3 = 4, kTY3 = 4, kTZ3 = 4;
 // A dispatch's grid holds at most 2^32 - 1 work-items (blocks x threads).
 constexpr int64_t kMaxWorkItems = 0xFFFFFFFFll;
 

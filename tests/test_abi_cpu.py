@@ -297,8 +297,8 @@ def test_meshes_beyond_one_dispatch_are_rejected_before_touching_the_device():
     assert b"too large" in lib.rtlbfs_last_error(None)
     ok2 = rt.make_mesh(2, (4096, 4096))
     assert lib.rtlbfs_workspace_bytes(C.byref(ok2), C.byref(o)) > 0
-    big3 = rt.make_mesh(3, (1024, 1024, 1024))     # 8.4e6 tiles of 512 threads: 4.3e9 work-items
-    ok3 = rt.make_mesh(3, (1000, 1000, 1000))      # 7.8e6 tiles: 4.0e9
+    big3 = rt.make_mesh(3, (1024, 1024, 1024))     # 2^24 tiles of 256 threads: 2^32 work-items
+    ok3 = rt.make_mesh(3, (1000, 1000, 1000))      # 1.6e7 tiles: 4.0e9
     assert lib.rtlbfs_workspace_bytes(C.byref(big3), C.byref(o)) == 0
     assert lib.rtlbfs_workspace_bytes(C.byref(ok3), C.byref(o)) > 0
     too_long = rt.make_mesh(2, ((1 << 20) + 1, 4))

@@ -373,8 +373,8 @@ def test_fp64_3d_cavity_parity(prec):
 
 
 def test_fp64_3d_48cube_tanh_parity_200_steps():
-    """A 48^3 tanh (phi = 1.8) cubic cavity at Ra = 1e5, 200 steps: six 8x4x4
-    tiles per x row, twelve in y and z, fields within 1e-12.  The oracle
+    """A 48^3 tanh (phi = 1.8) cubic cavity at Ra = 1e5, 200 steps: twelve
+    4x4x4 tiles along each axis, fields within 1e-12.  The oracle
     needs about a minute."""
     s, o = make_pair(3, (48, 48, 48), (1.8, 1.8, 1.8), **DHC3, Ra=1e5, noise=1e-3)
     s.step(200)
