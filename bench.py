@@ -817,16 +817,19 @@ def annulus_solver(rt, Ra, precision, **opts):
 
 
 def annulus_bench(rt, torch, steps, warmup):
-    """Time per step of the three body-fitted 3D kernels on the Sec. 4.5
-    wedge (28,800 cells), Ra = 1e5, FP32 deviation and FP64 plain, residual
-    once per KERNEL_CHUNK steps."""
+    """Time per step of the body-fitted 3D step on the Sec. 4.5 wedge (28,800
+    cells), Ra = 1e5, FP32 deviation and FP64 plain, residual once per
+    KERNEL_CHUNK steps: the fused single-layer kernel (one launch per step,
+    the default on this mesh) and, for comparison, the three-launch path
+    (opts.tile = 1)."""
     out = {"workload": "annulus 120x1x240 wedge Ra=1e5 (Sec. 4.5)", "cells": 120 * 240}
-    for name, prec in (("fp32_dev", rt.FP32_DEV), ("fp64_plain", rt.FP64_PLAIN)):
-        s, _, _ = annulus_solver(rt, 1e5, prec, residual_every=KERNEL_CHUNK, mass_fix_every=-1)
+    for name, prec, tile in (("fp32_dev", rt.FP32_DEV, 0), ("fp64_plain", rt.FP64_PLAIN, 0),
+                             ("fp32_dev_three_kernels", rt.FP32_DEV, 1), ("fp64_plain_three_kernels", rt.FP64_PLAIN, 1)):
+        s, _, _ = annulus_solver(rt, 1e5, prec, residual_every=KERNEL_CHUNK, mass_fix_every=-1, tile=tile)
         s.step(max(warmup, KERNEL_CHUNK))
         s.sync()
         ms = timed(torch, s, max(KERNEL_CHUNK, steps - steps % KERNEL_CHUNK))
-        out[name] = {"ms_per_step": ms, "value": s.cells / (ms * 1e-3)}
+        out[name] = {"ms_per_step": ms, "value": s.cells / (ms * 1e-3), "tile": [s.info.tile_x, s.info.tile_z]}
         del s
         torch.cuda.empty_cache()
     return out

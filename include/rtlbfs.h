@@ -343,8 +343,13 @@ size_t rtlbfs_curv3_workspace_bytes(const rtlbfs_curv3_mesh *mesh, const rtlbfs_
 
 /* Create a solver on a 3D body-fitted mesh; nu, chi, beta_g given directly.
  * The state starts at rest with rho = 1 and T = T_ref (+ opts->noise_amp
- * noise).  Options, workspace, stream and errors as for rtlbfs_curv_create
- * (opts->tile must be 0).  The handle works with the single-domain entry
+ * noise).  Options, workspace, stream and errors as for rtlbfs_curv_create,
+ * except opts->tile: 0 takes one fused launch per step (tile and halo staged
+ * in LDS) when axis j is periodic with a single cell and axes i and k are
+ * walled (the single-layer wedge of Sec. 4.5), three launches (per-cell
+ * gradients, per-face fluxes, per-cell update) otherwise; 1 forces the three
+ * launches; 2 forces the fused launch and is EINVAL on other meshes.  Both
+ * compute every face with the same arithmetic.  The handle works with the single-domain entry
  * points and rtlbfs_wall_heat (sides 0..5); rtlbfs_nusselt returns
  * RTLBFS_EUNSUPPORTED. */
 int rtlbfs_curv3_create(const rtlbfs_curv3_mesh *mesh, double nu, double chi, double beta_g,

@@ -5,9 +5,8 @@
 //
 // Each face carries its unit normal n, a tangent t1 (the face's first edge
 // without its normal part) and t2 = n x t1; the D3Q19 lattice of Fig. 1 is
-// aligned with (n, t1, t2).  A step is three launches over HBM buffers, one
-// thread per item (the meshes of this setting are small, and each pass is a
-// plain streaming loop):
+// aligned with (n, t1, t2).  On a general mesh a step is three launches
+// over HBM buffers, one thread per item:
 //   k_c3_grad    per cell: primitives and Eq. 55 gradients, sum over the six
 //                faces of phi_S S_out / dV with Eq. 56 face values;
 //   k_c3_flux    per face: the interior-face flux in the face frame (the
@@ -16,6 +15,8 @@
 //                the wall closure; area-weighted, global components;
 //   k_c3_update  per cell: divergence, buoyancy along `up`, forward Euler,
 //                stochastic rounding of the FP32 state, Eq. 65 partials.
+// On the single-layer wedge (j periodic with one cell, i and k walled) one
+// fused launch, k_c3_layer, does all three in LDS per tile.
 // Across a periodic side the neighbour is the image of the cell on the other
 // side, rotated by -alpha (low side) or +alpha (high side) about z: its
 // velocity as a vector, its velocity gradient as R G R^T.  Every face,
@@ -364,6 +365,52 @@ __global__ void __launch_bounds__(kC3Threads) k_c3_flux(Domain d, Curv3Geo g, co
     for (int p = 0; p < 5; ++p) out[p * g.nfaces + t] = F[p];
 }
 
+// Divergence, buoyancy along `up`, forward Euler and (FP32) stochastic
+// rounding of cell c, stored to Uout; on residual steps also the cell's
+// Eq. 65 terms and divergence flag in acc.  P holds the cell's primitives at
+// the old time level (velocities only needed when RES), old its stored
+// state, div the sum over the axes of low-face minus high-face area-weighted
+// fluxes, iv = 1/dV.
+template <typename R, bool DEV, bool RES>
+__device__ __forceinline__ void c3_update_cell(const Domain &d, const Curv3Geo &g, int c, const R (&P)[5],
+                                               const R (&old)[5], const R (&div)[5], R iv, uint32_t key,
+                                               R *__restrict__ Uout, double (&acc)[kPartials]) {
+    const int64_t N = d.fstride;
+    const Phys<R> &ph = make_phys<R>(d);
+    const R rP = P[0], TP = P[4];
+    const R rhoP = DEV ? (R)1 + rP : rP;
+    const R dtR = ph.dt;
+    const R dt_dV = dtR * iv;
+    const R Fb = dtR * ph.bg * rhoP * (TP - ph.Tref_s);
+    R Un[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        const R src = (p >= 1 && p <= 3) ? Fb * c3_up<R>(g, p - 1) : (R)0;
+        const R inc = dt_dV * div[p] + src;
+        if (sizeof(R) == 4 && d.sround) Un[p] = sr_add(old[p], inc, sr_hash((uint32_t)c, key * 5u + p));
+        else Un[p] = old[p] + inc;
+        Uout[p * N + c] = Un[p];
+    }
+    if (RES) {
+        const double rn = (double)Un[0];
+        const double rhon = DEV ? 1.0 + rn : rn;
+        double an = 0.0, ao = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double vn = (double)Un[1 + a] / rhon, vo = (double)P[1 + a];
+            an += vn * vn;
+            ao += vo * vo;
+        }
+        an = sqrt(an);
+        ao = sqrt(ao);
+        const double Tn = (double)Un[4] / rhon + (DEV ? kT0 : 0.0), To = (double)TP + (DEV ? kT0 : 0.0);
+        acc[0] = fabs(an - ao);
+        acc[1] = an;
+        acc[2] = fabs(Tn - To);
+        acc[3] = Tn;
+        acc[4] = (an * an < d.guard_u2) && (Tn == Tn) && (fabs(Tn) < 1e30) ? 0.0 : 1.0;
+    }
+}
+
 template <typename R, bool DEV, bool RES>
 __global__ void __launch_bounds__(kC3Threads) k_c3_update(Domain d, Curv3Geo g, const R *__restrict__ Uin,
                                                    R *__restrict__ Uout, double *__restrict__ parts,
@@ -390,40 +437,11 @@ __global__ void __launch_bounds__(kC3Threads) k_c3_update(Domain d, Curv3Geo g, 
             for (int p = 0; p < 5; ++p) div[p] += fl[p * g.nfaces + flo] - fl[p * g.nfaces + fhi];
             base += g.sf[a];
         }
-        const Phys<R> &ph = make_phys<R>(d);
         const R *pr = (const R *)g.prim;
-        const R rP = pr[c], TP = pr[4 * d.cells + c];
-        const R rhoP = DEV ? (R)1 + rP : rP;
-        const R dtR = ph.dt;
-        const R dt_dV = dtR * ((const R *)g.inv_vol)[c];
-        const R Fb = dtR * ph.bg * rhoP * (TP - ph.Tref_s);
-        R Un[5];
-#pragma unroll
-        for (int p = 0; p < 5; ++p) {
-            const R src = (p >= 1 && p <= 3) ? Fb * c3_up<R>(g, p - 1) : (R)0;
-            const R inc = dt_dV * div[p] + src;
-            if (sizeof(R) == 4 && d.sround) Un[p] = sr_add(old[p], inc, sr_hash((uint32_t)c, key * 5u + p));
-            else Un[p] = old[p] + inc;
-            Uout[p * N + c] = Un[p];
-        }
-        if (RES) {
-            const double rn = (double)Un[0];
-            const double rhon = DEV ? 1.0 + rn : rn;
-            double an = 0.0, ao = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                const double vn = (double)Un[1 + a] / rhon, vo = (double)pr[(1 + a) * d.cells + c];
-                an += vn * vn;
-                ao += vo * vo;
-            }
-            an = sqrt(an);
-            ao = sqrt(ao);
-            const double Tn = (double)Un[4] / rhon + (DEV ? kT0 : 0.0), To = (double)TP + (DEV ? kT0 : 0.0);
-            acc[0] = fabs(an - ao);
-            acc[1] = an;
-            acc[2] = fabs(Tn - To);
-            acc[3] = Tn;
-            acc[4] = (an * an < d.guard_u2) && (Tn == Tn) && (fabs(Tn) < 1e30) ? 0.0 : 1.0;
-        }
+        R P[5] = {pr[c], (R)0, (R)0, (R)0, pr[4 * d.cells + c]};
+        if (RES)
+            for (int a = 1; a <= 3; ++a) P[a] = pr[a * d.cells + c];
+        c3_update_cell<R, DEV, RES>(d, g, c, P, old, div, ((const R *)g.inv_vol)[c], key, Uout, acc);
     }
     if (RES) {
         block_sums<kPartials>(acc, sred);
@@ -431,6 +449,305 @@ __global__ void __launch_bounds__(kC3Threads) k_c3_update(Domain d, Curv3Geo g, 
             for (int m = 0; m < kPartials; ++m) parts[(int64_t)blockIdx.x * kPartials + m] = acc[m];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
+}
+
+// Fused step for a single-layer wedge: axis j periodic with one cell (its
+// images are the cell itself, rotated by -+alpha about z) and walls on axes
+// i and k, the setting of Sec. 4.5.  A TX x TZ tile with a 2-cell halo in i
+// and k then holds every value the step reads, and one launch does the work
+// of the three kernels above, with their arithmetic:
+//   load      every global read of the step at once: the state of the box,
+//             the face records of the gradient and face phases, 1/dV;
+//             primitives of the box and conserved state of the tile to LDS;
+//   gradient  Eq. 55 for the tile plus a 1-cell halo (as k_c3_grad);
+//   faces     the i- and k-faces of the tile and both j-faces of each of its
+//             cells, each face once (as k_c3_flux);
+//   update    divergence, source, forward Euler (as k_c3_update).
+template <int TX, int TZ>
+constexpr int c3_layer_threads() {
+    constexpr int nb = (TX + 4) * (TZ + 4);
+    constexpr int nf = (TX + 1) * TZ + TX * (TZ + 1) + 2 * TX * TZ;
+    return ((nb > nf ? nb : nf) + 63) / 64 * 64;
+}
+
+constexpr int kC3LayerTX = 16, kC3LayerTZ = 4;  // tile of the fused kernel
+
+template <typename R, bool DEV, bool TL, bool RES, int TX, int TZ>
+__global__ void __launch_bounds__((c3_layer_threads<TX, TZ>()))
+    k_c3_layer(Domain d, Curv3Geo g, const R *__restrict__ Uin, R *__restrict__ Uout, double *__restrict__ parts,
+               const uint32_t *__restrict__ ctr_in, uint32_t *__restrict__ ctr_out) {
+    constexpr int NT = c3_layer_threads<TX, TZ>();
+    constexpr int BX = TX + 4, NB = (TX + 4) * (TZ + 4);  // box: tile + 2-cell halo in i and k
+    constexpr int GX = TX + 2, NG = (TX + 2) * (TZ + 2);  // gradients: tile + 1-cell halo
+    constexpr int NFI = (TX + 1) * TZ, NFK = TX * (TZ + 1), NF = NFI + NFK + 2 * TX * TZ;
+    constexpr int NC = TX * TZ;
+    static_assert(NB <= NT && NF <= NT && NG <= NT && NC <= NT, "every phase is one pass of the block");
+    __shared__ R sp[5 * NB];   // primitives of the box
+    __shared__ R su[5 * NC];   // stored state of the tile
+    __shared__ R sg[15 * NG];  // gradients, [p * 3 + axis]
+    __shared__ R sf[5 * NF];   // area-weighted fluxes: i-faces, k-faces, then (j = 0, j = 1) per cell
+    __shared__ double sred[kPartials * (NT / 64)];
+    const uint32_t key = *ctr_in;
+    const int n0 = d.n[0], n2 = d.n[2];
+    const int ntx = (n0 + TX - 1) / TX;
+    const int i0 = ((int)blockIdx.x % ntx) * TX, k0 = ((int)blockIdx.x / ntx) * TZ;
+    const int tid = threadIdx.x;
+    const int64_t N = d.fstride;
+    const R *__restrict__ ivp = (const R *)g.inv_vol;
+
+    // ---- load: every global read of the step, issued before the first use
+    const int bi = tid % BX, bk = tid / BX;  // box cell
+    const int bgi = i0 - 2 + bi, bgk = k0 - 2 + bk;
+    const bool lb = tid < NB && bgi >= 0 && bgi < n0 && bgk >= 0 && bgk < n2;  // beyond a wall: never read
+    R u[5];
+    if (lb) {
+        const int c = bgk * n0 + bgi;
+#pragma unroll
+        for (int p = 0; p < 5; ++p) u[p] = Uin[p * N + c];
+    }
+    const int gi = tid % GX, gk = tid / GX;  // gradient cell
+    const int ggi = i0 - 1 + gi, ggk = k0 - 1 + gk;
+    const bool lg = tid < NG && ggi >= 0 && ggi < n0 && ggk >= 0 && ggk < n2;
+    R gr[6][5];  // its six faces (a, hi): n, dS, wL
+    R giv = (R)0;
+    if (lg) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int hi = 0; hi < 2; ++hi) {
+                int fq[3] = {ggi, 0, ggk};
+                fq[a] += hi;
+                const int64_t st = g.sf[a];
+                const R *rec = (const R *)g.f[a] + c3_face(d, a, fq[0], fq[1], fq[2]);
+                gr[2 * a + hi][0] = rec[kC3Nx * st];
+                gr[2 * a + hi][1] = rec[kC3Ny * st];
+                gr[2 * a + hi][2] = rec[kC3Nz * st];
+                gr[2 * a + hi][3] = rec[kC3DS * st];
+                gr[2 * a + hi][4] = rec[kC3WL * st];
+            }
+        giv = ivp[ggk * n0 + ggi];
+    }
+    // face of this thread: family fa (0: i, 1: j, 2: k), tile position, j side
+    int fa, fx, fz, fj = 0;
+    if (tid < NFI) {
+        fa = 0;
+        fx = tid % (TX + 1);
+        fz = tid / (TX + 1);
+    } else if (tid < NFI + NFK) {
+        fa = 2;
+        fx = (tid - NFI) % TX;
+        fz = (tid - NFI) / TX;
+    } else {
+        const int q = tid - NFI - NFK;
+        fa = 1;
+        fx = (q >> 1) % TX;
+        fz = (q >> 1) / TX;
+        fj = q & 1;
+    }
+    const int fgi = i0 + fx, fgk = k0 + fz;
+    const bool lf = tid < NF && (fa == 0 ? (fgi <= n0 && fgk < n2) : (fa == 2 ? (fgi < n0 && fgk <= n2) : (fgi < n0 && fgk < n2)));
+    R fr[13];  // n, t1, dS, dL, tL1, tL2, dR, tR1, tR2
+    if (lf) {
+        const int fq1 = fa == 1 ? fj : 0;
+        const R *rec = (const R *)pick3(fa, g.f) + c3_face(d, fa, fgi, fq1, fgk);
+        const int64_t st = pick3(fa, g.sf);
+#pragma unroll
+        for (int m = 0; m < 13; ++m) fr[m] = rec[(kC3Nx + m) * st];
+    }
+    const int ux = tid % TX, uz = tid / TX;  // update cell
+    const bool lu = tid < NC && i0 + ux < n0 && k0 + uz < n2;
+    const R uiv = lu ? ivp[(k0 + uz) * n0 + i0 + ux] : (R)0;
+    if (lb) {
+        const R inv = recip<R>(DEV ? (R)1 + u[0] : u[0]);
+        sp[tid] = u[0];
+#pragma unroll
+        for (int p = 1; p < 5; ++p) sp[p * NB + tid] = u[p] * inv;
+        const int ti = bi - 2, tk = bk - 2;
+        if (ti >= 0 && ti < TX && tk >= 0 && tk < TZ)
+#pragma unroll
+            for (int p = 0; p < 5; ++p) su[p * NC + tk * TX + ti] = u[p];
+    }
+    __syncthreads();
+
+    // ---- gradients (k_c3_grad with neighbours from LDS)
+    if (lg) {
+        const int b = (gk + 1) * BX + gi + 1;  // this cell in the box
+        R P[5];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) P[p] = sp[p * NB + b];
+        R acc[5][3];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) acc[p][0] = acc[p][1] = acc[p][2] = (R)0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int hi = 0; hi < 2; ++hi) {
+                const R *r5 = gr[2 * a + hi];
+                const R so = hi ? (R)1 : (R)-1;
+                const R sx = so * r5[0] * r5[3], sy = so * r5[1] * r5[3], sz = so * r5[2] * r5[3];
+                // neighbour: along j the cell itself rotated; along i, k the box cell (a wall reads the cell)
+                bool wall = false;
+                int nb = b;
+                R cr = (R)1, sr = (R)0;
+                if (a == 1) {
+                    cr = (R)g.rc[1];
+                    sr = (R)(hi ? g.rs[1] : -g.rs[1]);
+                } else if (a == 0) {
+                    const int ni = ggi + (hi ? 1 : -1);
+                    wall = ni < 0 || ni >= n0;
+                    nb = wall ? b : b + (hi ? 1 : -1);
+                } else {
+                    const int nk = ggk + (hi ? 1 : -1);
+                    wall = nk < 0 || nk >= n2;
+                    nb = wall ? b : b + (hi ? BX : -BX);
+                }
+                R Q[5];
+#pragma unroll
+                for (int p = 0; p < 5; ++p) Q[p] = sp[p * NB + nb];
+                R uq[3] = {Q[1], Q[2], Q[3]};
+                rot_z<R>(cr, sr, uq);
+                Q[1] = uq[0];
+                Q[2] = uq[1];
+                Q[3] = uq[2];
+                const R wL = r5[4];
+                const int side = 2 * a + hi;
+                const R Tw = d.kind[side] == kIsothermal ? wall_T<R>(d, side) : P[4];
+                const R pw[5] = {P[0], (R)0, (R)0, (R)0, Tw};
+                R phi[5];
+#pragma unroll
+                for (int p = 0; p < 5; ++p) {
+                    const R pin = hi ? wL * P[p] + ((R)1 - wL) * Q[p] : wL * Q[p] + ((R)1 - wL) * P[p];
+                    phi[p] = wall ? pw[p] : pin;
+                }
+#pragma unroll
+                for (int p = 0; p < 5; ++p) {
+                    acc[p][0] += phi[p] * sx;
+                    acc[p][1] += phi[p] * sy;
+                    acc[p][2] += phi[p] * sz;
+                }
+            }
+#pragma unroll
+        for (int p = 0; p < 5; ++p)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sg[(p * 3 + a) * NG + tid] = acc[p][a] * giv;
+    }
+    __syncthreads();
+
+    // ---- faces (k_c3_flux with cells from LDS)
+    if (lf) {
+        // low and high cells (global i, k), clamped to the fluid cell at a wall;
+        // the j-faces join the cell and its image rotated by -alpha (j = 0) or +alpha (j = 1)
+        int li = fgi, lk = fgk, hi_ = fgi, hk = fgk;
+        R cl = (R)1, sl = (R)0, ch = (R)1, sh = (R)0;
+        bool interior = true, low = false;
+        if (fa == 0) {
+            interior = fgi > 0 && fgi < n0;
+            low = fgi == 0;
+            li = fgi > 0 ? fgi - 1 : 0;
+            hi_ = fgi < n0 ? fgi : n0 - 1;
+        } else if (fa == 2) {
+            interior = fgk > 0 && fgk < n2;
+            low = fgk == 0;
+            lk = fgk > 0 ? fgk - 1 : 0;
+            hk = fgk < n2 ? fgk : n2 - 1;
+        } else {
+            low = fj == 0;
+            const R rc = (R)g.rc[1], rs = (R)g.rs[1];
+            cl = fj == 0 ? rc : (R)1;
+            sl = fj == 0 ? -rs : (R)0;
+            ch = fj == 0 ? (R)1 : rc;
+            sh = fj == 0 ? (R)0 : rs;
+        }
+        const int bl = (lk - k0 + 2) * BX + li - i0 + 2, bh = (hk - k0 + 2) * BX + hi_ - i0 + 2;
+        const int gl = (lk - k0 + 1) * GX + li - i0 + 1, gh = (hk - k0 + 1) * GX + hi_ - i0 + 1;
+        R PA[5], PB[5], GA[5][3], GB[5][3];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            PA[p] = sp[p * NB + bl];
+            PB[p] = sp[p * NB + bh];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                GA[p][a] = sg[(p * 3 + a) * NG + gl];
+                GB[p][a] = sg[(p * 3 + a) * NG + gh];
+            }
+        }
+        // the fluid cell of a wall face is a cell of this tile; other faces
+        // read their own cell's slot, unused
+        const int wi = low ? hi_ : li, wk = low ? hk : lk;
+        const int wt = interior ? (fa == 1 ? fz * TX + fx : 0) : (wk - k0) * TX + (wi - i0);
+        const R rP = su[wt], eP = su[4 * NC + wt];
+        const R mw[3] = {su[NC + wt], su[2 * NC + wt], su[3 * NC + wt]};
+        R e[3][3];
+        e[0][0] = fr[kC3Nx - kC3Nx];
+        e[0][1] = fr[kC3Ny - kC3Nx];
+        e[0][2] = fr[kC3Nz - kC3Nx];
+        e[1][0] = fr[kC3T1x - kC3Nx];
+        e[1][1] = fr[kC3T1y - kC3Nx];
+        e[1][2] = fr[kC3T1z - kC3Nx];
+        const R dS = fr[kC3DS - kC3Nx], dL = fr[kC3DL - kC3Nx], dR = fr[kC3DR - kC3Nx];
+        const R tl1 = fr[kC3TL1 - kC3Nx], tl2 = fr[kC3TL2 - kC3Nx], tr1 = fr[kC3TR1 - kC3Nx];
+        const R tr2 = fr[kC3TR2 - kC3Nx];
+        e[2][0] = e[0][1] * e[1][2] - e[0][2] * e[1][1];  // t2 = n x t1
+        e[2][1] = e[0][2] * e[1][0] - e[0][0] * e[1][2];
+        e[2][2] = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+        const Phys<R> &ph = make_phys<R>(d);
+        R F[5];
+        {
+            c3_rotate<R>(cl, sl, PA, GA);
+            c3_rotate<R>(ch, sh, PB, GB);
+            Side<R, 3> A, B;
+            side_in_frame3<R>(PA, GA, e, tl1, tl2, A);
+            side_in_frame3<R>(PB, GB, e, tr1, tr2, B);
+            const R up[3] = {c3_up<R>(g, 0), c3_up<R>(g, 1), c3_up<R>(g, 2)};
+            frame_flux3<R, DEV, TL>(A, B, dL, dR, e, up, d.force_pred != 0, dS, ph, F);
+        }
+        {
+            const int side = 2 * fa + (low ? 0 : 1);
+            R ml[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) ml[k] = mw[0] * e[k][0] + mw[1] * e[k][1] + mw[2] * e[k][2];
+            R G[5], Fw[5];
+            const R Tw = sizeof(R) == 4 ? (R)pick6(side, d.Twf) : (R)pick6(side, d.Tw);
+            wall_flux<R, 3, DEV>(rP, ml, eP, low ? (R)-1 : (R)1, low ? dR : dL, pick6(side, d.kind) == kIsothermal,
+                                 Tw, ph, G);
+            Fw[0] = G[0] * dS;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Fw[1 + b] = (G[1] * e[0][b] + G[2] * e[1][b] + G[3] * e[2][b]) * dS;
+            Fw[4] = G[4] * dS;
+#pragma unroll
+            for (int p = 0; p < 5; ++p) F[p] = interior ? F[p] : Fw[p];
+        }
+#pragma unroll
+        for (int p = 0; p < 5; ++p) sf[p * NF + tid] = F[p];
+    }
+    __syncthreads();
+
+    // ---- update (k_c3_update with fluxes from LDS)
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (lu) {
+        const int c = (k0 + uz) * n0 + i0 + ux;
+        const int b = (uz + 2) * BX + ux + 2;
+        R P[5], old[5], div[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+        for (int p = 0; p < 5; ++p) {
+            P[p] = sp[p * NB + b];
+            old[p] = su[p * NC + tid];
+        }
+        const int fi = uz * (TX + 1) + ux, fk = NFI + uz * TX + ux, fjl = NFI + NFK + 2 * tid;
+#pragma unroll
+        for (int p = 0; p < 5; ++p) div[p] += sf[p * NF + fi] - sf[p * NF + fi + 1];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) div[p] += sf[p * NF + fjl] - sf[p * NF + fjl + 1];
+#pragma unroll
+        for (int p = 0; p < 5; ++p) div[p] += sf[p * NF + fk] - sf[p * NF + fk + TX];
+        c3_update_cell<R, DEV, RES>(d, g, c, P, old, div, uiv, key, Uout, acc);
+    }
+    if (RES) {
+        block_sums<kPartials>(acc, sred);
+        if (tid == 0)
+            for (int m = 0; m < kPartials; ++m) parts[(int64_t)blockIdx.x * kPartials + m] = acc[m];
+    }
+    if (blockIdx.x == 0 && tid == 0) *ctr_out = key + 1u;
 }
 
 // Wall heat of one side: {sum (T_w - T_P)/d dS, sum dS} (single block, FP64

@@ -194,6 +194,7 @@ struct rtlbfs_handle {
     std::vector<double> ccx, ccy, carea;            // host copy of the cell geometry
     // 3D body-fitted mesh (rtlbfs_curv3_create)
     bool curv3 = false;
+    bool c3_layer = false;  // 3D body-fitted: the fused single-layer kernel (else three kernels)
     Curv3Geo c3{};
     const double *c3rec64[3] = {nullptr, nullptr, nullptr};  // FP64 face records (diagnostics)
     std::vector<double> c3cx, c3cy, c3cz, c3vol;
@@ -338,8 +339,19 @@ bool curv_launches_fit(int ni, int nj) {
     return true;
 }
 
+// The fused single-layer kernel applies: one periodic cell along j, walls
+// along i and k.
+bool c3_is_layer(const int n[3], const int kind[6]) {
+    return n[1] == 1 && kind[2] == RTLBFS_PERIODIC && kind[0] != RTLBFS_PERIODIC && kind[4] != RTLBFS_PERIODIC;
+}
+
+int c3_layer_blocks(const int n[3]) {
+    return ((n[0] + kC3LayerTX - 1) / kC3LayerTX) * ((n[2] + kC3LayerTZ - 1) / kC3LayerTZ);
+}
+
 // Blocks of one step launch of the handle (rows of residual partials).
 int handle_blocks(const rtlbfs_t h, int tile) {
+    if (h->curv3 && h->c3_layer) return c3_layer_blocks(h->mesh.n);
     if (h->curv3) return (int)((h->lay.cells + kC3Threads - 1) / kC3Threads);
     return h->curv ? curv_blocks(h->mesh, tile) : step_blocks(h->mesh, tile);
 }
@@ -348,6 +360,13 @@ template <typename R, bool DEV, bool TL>
 hipError_t launch_curv3(rtlbfs_t h, int src, bool res, hipStream_t s) {
     const R *Uin = (const R *)h->U(src);
     R *Uout = (R *)h->U(src ^ 1);
+    if (h->c3_layer) {
+        constexpr int TX = kC3LayerTX, TZ = kC3LayerTZ, lt = c3_layer_threads<TX, TZ>();
+        const int lb = c3_layer_blocks(h->mesh.n);
+        if (res) k_c3_layer<R, DEV, TL, true, TX, TZ><<<lb, lt, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
+        else k_c3_layer<R, DEV, TL, false, TX, TZ><<<lb, lt, 0, s>>>(h->dom, h->c3, Uin, Uout, h->parts(), h->ctr() + src, h->ctr() + (src ^ 1));
+        return hipGetLastError();
+    }
     constexpr int nt = kC3Threads;
     const int cb = (int)((h->lay.cells + nt - 1) / nt), fb = (int)((h->c3.nfaces + nt - 1) / nt);
     k_c3_grad<R, DEV><<<cb, nt, 0, s>>>(h->dom, h->c3, Uin);
@@ -648,7 +667,8 @@ Curv3Layout make_curv3_layout(const int n[3], int precision) {
     off += align256((size_t)15 * cells * es);
     l.off_flux = off;
     off += align256((size_t)5 * nfaces * es);
-    l.nparts = std::max<int>(kRedBlocks, (int)((cells + kC3Threads - 1) / kC3Threads));  // one per update block
+    // one row per update block of either path
+    l.nparts = std::max<int>(kRedBlocks, std::max<int>((int)((cells + kC3Threads - 1) / kC3Threads), c3_layer_blocks(n)));
     l.off_parts = off;
     off += align256(sizeof(double) * (size_t)l.nparts * 8);
     l.off_red = off;
@@ -995,7 +1015,12 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
     for (int a = 0; a < 3; ++a) out->length[a] = a < h->mesh.dim ? h->length[a] : 1.0;
     out->precision = h->opts.precision;
     for (int t = 0; t < kNumTiles2; ++t) out->tune_ms[t] = h->tune_ms[t];
-    if (h->curv3) {
+    if (h->curv3 && h->c3_layer) {
+        out->tile_x = kC3LayerTX;  // fused kernel: one TX x 1 x TZ tile per block
+        out->tile_y = 1;
+        out->tile_z = kC3LayerTZ;
+        out->steps_per_launch = 1;
+    } else if (h->curv3) {
         out->tile_x = kC3Threads;  // one thread per cell or face, kC3Threads per block
         out->tile_y = 1;
         out->tile_z = 1;
@@ -1310,7 +1335,7 @@ int rtlbfs_curv3_create(const rtlbfs_curv3_mesh *mesh, double nu, double chi, do
     if (o.precision != RTLBFS_FP64_PLAIN && o.precision != RTLBFS_FP32_DEV && o.precision != RTLBFS_FP64_DEV)
         return reject("unknown precision");
     if (o.method != RTLBFS_METHOD_RTLBFS && o.method != RTLBFS_METHOD_TLBFS) return reject("unknown opts.method");
-    if (o.tile != 0) return reject("opts.tile must be 0 on a body-fitted mesh");
+    if (o.tile < 0 || o.tile > 2) return reject("opts.tile out of range for a 3D body-fitted mesh (0..2)");
     if (!(nu > 0.0) || !(chi > 0.0) || !(beta_g >= 0.0)) return reject("nu, chi > 0, beta_g >= 0");
     if (!(o.dtl >= 0.0) || !(o.dt >= 0.0)) return reject("dtl and dt must be >= 0");
     if (!(o.max_mach >= 0.0) || o.max_mach > 10.0) return reject("opts.max_mach out of range");
@@ -1320,6 +1345,11 @@ int rtlbfs_curv3_create(const rtlbfs_curv3_mesh *mesh, double nu, double chi, do
     if (rc != RTLBFS_OK) {
         g_create_err = why;
         return rc;
+    }
+    const bool layer = c3_is_layer(cp.n, bc->kind);
+    if (o.tile == 2 && !layer) {
+        g_create_err = "opts.tile 2 (fused kernel) needs a single periodic cell layer along j and walls along i and k";
+        return RTLBFS_EINVAL;
     }
     Problem P;
     P.mesh.dim = 3;
@@ -1340,6 +1370,7 @@ int rtlbfs_curv3_create(const rtlbfs_curv3_mesh *mesh, double nu, double chi, do
     rtlbfs_t h = new (std::nothrow) rtlbfs_handle();
     if (!h) return RTLBFS_ENOMEM;
     h->curv3 = true;
+    h->c3_layer = o.tile == 2 || (o.tile == 0 && layer);
     h->mesh = P.mesh;
     h->bc = P.bc;
     if (o.residual_every <= 0) o.residual_every = 100;

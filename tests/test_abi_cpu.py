@@ -247,8 +247,8 @@ def _c3_create(X, Y, Z, bc, nu=0.1, opts=None):
     return rc, h
 
 
-@pytest.mark.parametrize("case", ["farfield", "pair", "rot_walled", "not_closed", "folded", "up", "tile", "nu",
-                                  "small"])
+@pytest.mark.parametrize("case", ["farfield", "pair", "rot_walled", "not_closed", "folded", "up", "tile",
+                                  "tile_not_layer", "nu", "small"])
 def test_curv3_create_rejects_invalid_problems_before_touching_the_device(case):
     import inputs
     X, Y, Z = inputs.annulus_wedge(5, 1, 4, 10.0, 15.0, 4.0, 0.1)
@@ -272,6 +272,10 @@ def test_curv3_create_rejects_invalid_problems_before_touching_the_device(case):
     elif case == "up":
         b.up[:] = [0.0, 0.5, 0.5]
     elif case == "tile":
+        kw["opts"] = rt.make_opts(tile=3)
+    elif case == "tile_not_layer":
+        # the fused kernel (tile 2) needs a single periodic cell layer: two cells of 0.05 rad here
+        X, Y, Z = inputs.annulus_wedge(5, 2, 4, 10.0, 15.0, 4.0, 0.05)
         kw["opts"] = rt.make_opts(tile=2)
     elif case == "nu":
         kw["nu"] = -1.0

@@ -147,3 +147,39 @@ def test_graph_replay_equals_eager_launches_3d():
     with pytest.raises(rt.RtlbfsError) as e:
         a.wall_heat(4)  # adiabatic
     assert e.value.code == rt.EINVAL
+
+
+@pytest.mark.parametrize("precision", [rt.FP64_PLAIN, rt.FP32_DEV])
+def test_fused_layer_kernel_equals_three_kernels(precision):
+    """A single-layer wedge (j periodic with one cell, walls along i and k)
+    runs one fused launch per step by default (opts.tile 0, or 2); opts.tile 1
+    forces the three-launch path.  From a random, non-axisymmetric state on a
+    21 x 1 x 27 wedge (ragged 16 x 4 tiles in i and k), both give the same
+    fields; the fused path also matches the oracle."""
+    X, Y, Z = wedge(nr=21, nz=27, dth=0.1)
+    bc = wedge_bc(1, 0.1)
+    kw = dict(rot=bc["rot"], Tw=bc["Tw"], up=bc["up"], T_ref=0.5, nu=0.06, chi=0.08, beta_g=bc["beta_g"],
+              precision=precision, dt=0.5, residual_every=20)
+    runs = {t: rt.Curv3Solver(X, Y, Z, bc["kind"], tile=t, **kw) for t in (0, 1, 2)}
+    assert (runs[0].info.tile_x, runs[0].info.tile_z) == (16, 4)
+    assert (runs[2].info.tile_x, runs[2].info.tile_z) == (16, 4)
+    assert runs[1].info.tile_x == 64 and runs[1].info.tile_z == 1
+    rho, u, T = inputs.random_state(runs[0].cells, 3, seed=31)
+    for s in runs.values():
+        s.set_state(rho, u, T)
+        s.step(150)
+    tol = FP64_TOL if precision == rt.FP64_PLAIN else 2e-6  # FP64: the oracle parity bar
+    for f in range(5):
+        a, b, c = runs[0].field(f), runs[1].field(f), runs[2].field(f)
+        assert np.array_equal(a, c), f
+        scale = max(np.abs(b - (1.0 if f == 0 else 0.0)).max(), 1e-3)
+        assert np.abs(a - b).max() <= tol * scale, (f, np.abs(a - b).max() / scale)
+    if precision == rt.FP64_PLAIN:
+        ra, rb = runs[0].residual(), runs[1].residual()
+        assert abs(ra[0] - rb[0]) <= 1e-9 * abs(rb[0]) and abs(ra[1] - rb[1]) <= 1e-9 * abs(rb[1])
+        s, o = make_pair(X, Y, Z, precision, **wedge_bc(1, 0.1))
+        s.set_state(rho, u, T)
+        o.set_prim(rho, u, T)
+        s.step(60)
+        o.step(60)
+        assert max(rel_errors(s, o)) <= FP64_TOL
