@@ -41,7 +41,7 @@ __global__ void __launch_bounds__((tile2_threads<TX, TY, NSUB>())) __attribute__
 }
 
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES, bool TL>
-__global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((amdgpu_waves_per_eu(5, 8))) k_step3d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
+__global__ void __launch_bounds__((tile3_threads<TX, TY, TZ>())) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 3, 8))) k_step3d(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
                                                 double *__restrict__ parts, const uint32_t *__restrict__ ctr_in,
                                                 uint32_t *__restrict__ ctr_out) {
     const uint32_t key = *ctr_in;

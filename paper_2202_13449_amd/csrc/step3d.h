@@ -46,7 +46,11 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                   "gradient, face and update phases are one pass of the block");
     __shared__ R sp[NPRIM][TT::NP];
     __shared__ R sg[NPRIM][3][TT::NG];
-    __shared__ R sf[NPRIM][TT::NF];
+    // The face fluxes reuse the gradients' LDS: every face has read its
+    // gradients before the barrier that precedes the first flux store.  The
+    // saving lets a third FP64 4 x 4 x 4 block onto a CU.
+    static_assert(TT::NF <= 3 * TT::NG, "the fluxes fit in the gradients' space");
+    R(*const sf)[TT::NF] = reinterpret_cast<R(*)[TT::NF]>(&sg[0][0][0]);
     __shared__ R sc[NPRIM][TT::NC];  // old conserved state of the tile cells
     __shared__ R sgeo[kGeoFields][TT::GEO];
     __shared__ double sred[kPartials * 16];
@@ -176,7 +180,11 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
 
     // Phase 3: every face once.  Per lane: normal axis ax with tangents
     // (t1, t2) in increasing order, face coordinates f (the high cell's tile
-    // coordinates), and the LDS strides of one step along ax.
+    // coordinates), and the LDS strides of one step along ax.  The
+    // area-weighted flux in global components waits in Fg until every face
+    // has read the gradients.
+    R Fg[5];
+    bool fvalid = false;
     if (tid < TT::NF) {
         const int ax = tid < TT::NF0 ? 0 : (tid < TT::NF0 + TT::NF1 ? 1 : 2);
         const int qq = tid - (ax == 0 ? 0 : (ax == 1 ? TT::NF0 : TT::NF0 + TT::NF1));
@@ -237,13 +245,18 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 else face_flux<R, 3, DEV>(A, B, dL, dR, fdir, ph, G);
             }
             // back to global components (mass, m_x, m_y, m_z, energy)
-            sf[0][tid] = G[0] * area;
-            sf[1][tid] = (ax == 0 ? G[1] : G[2]) * area;
-            sf[2][tid] = (ax == 0 ? G[2] : (ax == 1 ? G[1] : G[3])) * area;
-            sf[3][tid] = (ax == 2 ? G[1] : G[3]) * area;
-            sf[4][tid] = G[4] * area;
+            Fg[0] = G[0] * area;
+            Fg[1] = (ax == 0 ? G[1] : G[2]) * area;
+            Fg[2] = (ax == 0 ? G[2] : (ax == 1 ? G[1] : G[3])) * area;
+            Fg[3] = (ax == 2 ? G[1] : G[3]) * area;
+            Fg[4] = G[4] * area;
+            fvalid = true;
         }
     }
+    __syncthreads();  // gradients read: their space now takes the fluxes
+    if (fvalid)
+#pragma unroll
+        for (int p = 0; p < 5; ++p) sf[p][tid] = Fg[p];
     __syncthreads();
 
     // Phase 4: divergence, Boussinesq source and update.
