@@ -126,7 +126,7 @@ typedef struct {
 typedef struct {
     double hot_avg, hot_max;   /* area-weighted mean and maximum over the hot wall */
     double cold_avg, cold_max; /* same over the cold wall */
-    double volume;             /* Eq. 69 along the heat axis: L/(chi dT) <rho u_a T - chi d_a T>, absolute T */
+    double volume;             /* Eq. 69 along the heat axis: L/(chi dT) <u_a T - chi d_a T>, absolute T */
 } rtlbfs_nu;
 
 typedef struct {

@@ -884,11 +884,10 @@ void orc_integrals(const orc_state *s, double *out)
  * volume Nusselt number of Eq. 69 generalised to that axis:
  *   wall:   Nu_P = (L/dT) (T_w - T_P)/d (hot),  (T_P - T_w)/d (cold),
  *           average weighted by face area, maximum over the wall;
- *   volume: Nu = L/(chi dT) * <s (rho u_a T - chi d_a T)>, with s = +1 when
- *           the hot wall is on the low side, absolute T, Eq. 55 gradient.
- *           Eq. 69 writes the advective part as u T at unit density; the
- *           energy flux the scheme transports is rho u T (the same in the
- *           incompressible limit). */
+ *   volume: Nu = L/(chi dT) * <s (u_a T - chi d_a T)>, exactly the
+ *           integrand of Eq. 69 (velocity times absolute temperature, no
+ *           density factor), with s = +1 when the hot wall is on the low
+ *           side and the Eq. 55 gradient of T. */
 int orc_nusselt(const orc_state *s, double *out)
 {
     const int D = s->D;
@@ -932,8 +931,7 @@ int orc_nusselt(const orc_state *s, double *out)
         }
         double dV = cell_volume(s, ijk);
         double Tabs = Tp + TREF;
-        double dens = dev ? 1.0 + s->prim[0][idx] : s->prim[0][idx];
-        double qa = dens * s->prim[1 + haxis][idx] * Tabs - s->c.chi * s->grad[D + 1][haxis][idx];
+        double qa = s->prim[1 + haxis][idx] * Tabs - s->c.chi * s->grad[D + 1][haxis][idx];
         vol_sum += (hot_hi ? -qa : qa) * dV;
         vol += dV;
     }

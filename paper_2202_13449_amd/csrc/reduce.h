@@ -85,9 +85,9 @@ __global__ void __launch_bounds__(256) k_nusselt(Domain d, const R *__restrict__
             fhi = (Tp * wN + T2 * wP) / (wP + wN);
         }
         const double dTda = (fhi - flo) / wP;
-        // advective part rho u_a T: the energy flux the scheme transports
-        // (Eq. 69's u T at unit density), absolute T
-        const double qa = rho * u[haxis] * (Tp + kT0) - d.chi * dTda;
+        // Eq. 69 integrand: u_a T with the absolute temperature (no density
+        // factor) minus chi times the temperature gradient
+        const double qa = u[haxis] * (Tp + kT0) - d.chi * dTda;
         acc[4] += (hot_hi ? -qa : qa) * vol;
         acc[5] += vol;
         for (int hi = 0; hi < 2; ++hi) {
