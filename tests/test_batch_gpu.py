@@ -74,3 +74,41 @@ def test_batch_graph_replay_equals_direct_launches():
     for k in range(len(MEMBERS)):
         for f in range(4):
             assert np.array_equal(a.field(k, f), c.field(k, f))
+
+
+def test_batch_with_a_512_tanh_member_equals_single_handles():
+    """A 512^2 tanh (phi = 1.5) cavity at Ra = 1e6, the largest member size
+    of the 256-cavity workload, batched with a small uniform one: both equal
+    their single-domain runs bit for bit (FP32 with stochastic rounding and
+    the mass fix, and FP64)."""
+    members = [((512, 512), (1.5, 1.5), 1e6, 0.71), ((64, 64), (0.0, 0.0), 1e4, 7.0)]
+    for precision in (rt.FP32_DEV, rt.FP64_PLAIN):
+        b = make_batch(precision, members=members, residual_every=40, mass_fix_every=100)
+        b.step(230)
+        for k, m in enumerate(members):
+            s = single(m, precision, residual_every=40, mass_fix_every=100)
+            s.step(230)
+            for f in range(4):
+                assert np.array_equal(b.field(k, f), s.field(f)), (precision, k, f)
+            assert b.residual(k) == s.residual()
+
+
+@pytest.mark.timeout(600)
+def test_full_256_cavity_work_list_equals_single_handles():
+    """The benchmarked batch itself: the 256 seeded cavities (side 64 to 512,
+    Ra 1e3 to 1e7, Pr 0.71 or 7, uniform or tanh; about 2.3e7 cells) in one
+    launch per step, FP32 deviation storage.  After 30 steps every member
+    equals its own single-domain run bit for bit."""
+    from paper_2202_13449_amd.workloads import batch_cavities, total_cells
+
+    wl = batch_cavities(256, seed=4)
+    members = [((m["n"], m["n"]), (m["stretch"], m["stretch"]), m["Ra"], m["Pr"]) for m in wl]
+    b = make_batch(rt.FP32_DEV, members=members, residual_every=10)
+    print("C4 work list:", len(members), "members,", total_cells(wl), "cells", flush=True)
+    b.step(30)
+    for k, m in enumerate(members):
+        s = single(m, rt.FP32_DEV, residual_every=10)
+        s.step(30)
+        for f in range(4):
+            assert np.array_equal(b.field(k, f), s.field(f)), (k, m, f)
+        s.close()

@@ -1,16 +1,19 @@
 """GPU parity: the HIP kernels (through the C ABI) against the FP64 oracle.
 
 Element-by-element comparison of the absolute primitive fields on the same
-seeded inputs.  Tolerance for the FP64 paths: max |gpu - oracle| / scale <=
-1e-12 per field, where the scale is max |oracle| for rho and T and
-max(max |u|, V_c) for the velocity components (V_c = Ma, the characteristic
-velocity of Eq. 63).  The kernels contract multiply-adds and sum fluxes in a
-different order; in plain storage the rounding of rho ~ 1 (1e-16) enters the
-pressure gradient every step, so early in a run, when |u| << V_c, the velocity
-differences measured against max |u| alone would reflect that rounding, not
-the scheme.  The FP32 deviation path is compared
-against the oracle's FP64 deviation form with a tolerance derived from FP32
-rounding, and on Nusselt numbers at steady state (1e-4 relative).
+seeded inputs.  Tolerance for the FP64 paths (RTLBFS and TLBFS): max |gpu -
+oracle| / scale <= 1e-12 per field.  The scale is max |oracle| for rho and
+T.  The velocity components share one scale, the largest of max |oracle
+u_a| over the components (the flow speed).  That speed is floored at V_c
+(= Ma, the characteristic velocity of Eq. 63) while the flow is still
+developing.  The long horizons (the 64^2 cavity at 20,000 steps, the 256^2
+cavity's 2,000-step prefix, the 48^3 cube) drop the floor.  The kernels
+contract multiply-adds and sum fluxes in a different order.  In plain storage
+the rounding of rho ~ 1 (1e-16) enters the pressure gradient every step, so
+early in a run, when |u| << V_c, the velocity differences against max |u|
+alone reflect that rounding, not the scheme.  The FP32 deviation path is
+compared against the oracle's FP64 deviation form with a tolerance derived
+from FP32 rounding, and on Nusselt numbers at steady state (1e-4 relative).
 """
 import numpy as np
 import pytest
@@ -22,6 +25,7 @@ from oracle import INIT_CONDUCTION, INIT_REST, Oracle, OracleConfig, physics_fro
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
+TLBFS_TOL = FP64_TOL  # measured about 3e-15, like RTLBFS
 
 
 def make_pair(dim, n, stretch, kind, Tdev, gaxis, Ra=1e4, Pr=0.71, Ma=0.1, precision=rt.FP64_PLAIN, seed=1,
@@ -47,11 +51,18 @@ def make_pair(dim, n, stretch, kind, Tdev, gaxis, Ra=1e4, Pr=0.71, Ma=0.1, preci
 
 
 def field_rel(s, o, dim, Vc=0.1):
+    """max |gpu - oracle| / scale per absolute primitive.  The scale is
+    max |oracle| (P14) for rho and T; the velocity is one vector field, so
+    its components share the scale max_a max |oracle u_a| (the largest speed
+    component), floored at Vc.  Vc = 0 gives the plain P14 scale, used once
+    the flow is developed."""
+    prim = [o.prim(f) for f in range(dim + 2)]
+    speed = max(float(np.abs(prim[f]).max()) for f in range(1, dim + 1))
     out = []
     for f in range(dim + 2):
-        a, b = s.field(f), o.prim(f)
-        scale = max(np.abs(b).max(), Vc if 1 <= f <= dim else 0.0, 1e-300)
-        out.append(float(np.abs(a - b).max() / scale))
+        a, b = s.field(f), prim[f]
+        scale = max(speed, Vc) if 1 <= f <= dim else float(np.abs(b).max())
+        out.append(float(np.abs(a - b).max() / max(scale, 1e-300)))
     return out
 
 
@@ -104,8 +115,9 @@ def test_fp64_c1_parity_20000_steps():
     s, o = make_pair(2, (64, 64), (0.0, 0.0), **DHC2, Ra=1e3, noise=1e-6)
     s.step(20000)
     o.step(20000)
-    rel = field_rel(s, o, 2)
-    print("64^2, 20000 steps: rel", rel, flush=True)
+    rel = field_rel(s, o, 2, Vc=0.0)
+    print("64^2, 20000 steps: rel (P14 scale)", rel, flush=True)
+    assert max(np.abs(o.prim(1)).max(), np.abs(o.prim(2)).max()) > 0.01  # developed: u L / chi ~ 3.6
     assert max(rel) <= FP64_TOL, rel
 
 
@@ -315,19 +327,27 @@ def test_divergence_is_reported_and_clears():
     assert np.isfinite(s.field(3)).all()
 
 
+_FULL_SIZE_ORACLE = {}
+
+
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("tile", [0, 6])
 def test_c2_full_size_prefix_fp64(tile):
     """256^2 tanh (phi = 1.5) cavity at Ra = 1e6, the benchmarked
     configuration, in the autotuned launch shape and in 16x16 with two steps
-    per launch: 100 steps compared cell by cell with the oracle."""
+    per launch: the 2,000-step prefix compared cell by cell with the oracle
+    (one oracle run, about 90 s, serves both shapes), on P14's scale
+    max |oracle| for every field."""
     s, o = make_pair(2, (256, 256), (1.5, 1.5), **DHC2, Ra=1e6, noise=1e-6, tile=tile)
-    s.step(100)
-    o.step(100)
-    rel = field_rel(s, o, 2)
+    print("C2 prefix, tile", (s.info.tile_x, s.info.tile_y, s.info.steps_per_launch), flush=True)
+    s.step(2000)
+    if "fp64" not in _FULL_SIZE_ORACLE:
+        o.step(2000)
+        _FULL_SIZE_ORACLE["fp64"] = o
+    o = _FULL_SIZE_ORACLE["fp64"]
+    rel = field_rel(s, o, 2, Vc=0.0)
+    print("C2 prefix 2000 steps: rel (P14 scale)", rel, "u max", np.abs(o.prim(1)).max(), flush=True)
     assert max(rel) <= FP64_TOL, rel
-
-
-_FULL_SIZE_ORACLE = {}
 
 
 @pytest.mark.parametrize("tile", [0, 6])
@@ -356,6 +376,58 @@ def test_c2_full_size_fp32_in_the_benchmarked_configuration(tile):
     assert max(own) <= 1e-5, own  # measured: about 4e-7
 
 
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP64_DEV])
+def test_buoyancy_in_the_update_only_parity(prec):
+    """The paper-literal placement of Eq. 64 (force in the cell update only,
+    opts.buoyancy_update_only = 1) against the oracle with the force left
+    out of the predicted momentum: a stretched cavity and the periodic
+    Rayleigh-Benard box, 600 steps, fields within 1e-12.  The two placements
+    differ by far more than that (checked on the oracle)."""
+    cases = [((2, (40, 30), (1.5, 1.5), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"]), dict(Ra=1e5, noise=1e-3)),
+             ((2, (48, 20), (0.0, 0.0), (0, 0, 1, 1), (0.0, 0.0, 0.5, -0.5), 1),
+              dict(Ra=5e4, noise=1e-3, init=INIT_CONDUCTION, seed=3))]
+    for args, kw in cases:
+        s = rt.Solver(*args, Ra=kw["Ra"], precision=prec, seed=kw.get("seed", 1), noise_amp=kw["noise"],
+                      init=kw.get("init", INIT_REST), buoyancy_update_only=1)
+        info = s.info
+        nu, chi, bg = physics_from_ra(kw["Ra"], 0.71, 0.1, info.L)
+        cfg = dict(n=args[1], stretch=args[2], bc=tuple(args[3]) + (0, 0), Tw=tuple(args[4]) + (0.0, 0.0),
+                   gravity_axis=args[5], nu=nu, chi=chi, beta_g=bg, dtl=info.dtl, dt=info.dt,
+                   deviation=0 if prec == rt.FP64_PLAIN else 1, init=kw.get("init", INIT_REST),
+                   seed=kw.get("seed", 1), noise_amp=kw["noise"])
+        lit = Oracle(OracleConfig(force_in_predictor=0, **cfg))
+        pred = Oracle(OracleConfig(force_in_predictor=1, **cfg))
+        s.step(600)
+        lit.step(600)
+        pred.step(600)
+        rel = field_rel(s, lit, 2)
+        apart = max(float(np.abs(lit.prim(f) - pred.prim(f)).max() / max(np.abs(pred.prim(f)).max(), 0.1))
+                    for f in (1, 2))
+        print("update-only force:", args[1], "rel", rel, "placements differ by", apart, flush=True)
+        assert apart > 1e-6
+        assert max(rel) <= FP64_TOL, rel
+
+
+@pytest.mark.parametrize("shape,stretch", [((64, 64), (0.0, 0.0)), ((256, 256), (1.5, 1.5))])
+def test_fp32_mass_drift_fix_on_cartesian_meshes(shape, stretch):
+    """P3 for the FP32 deviation storage on the Cartesian path: with the
+    mass-drift correction (every 1,000 steps, the default) the total mass
+    stays within 1e-7 of its initial value over 20,000 steps, checked after
+    every 2,000; the FP64 integral is formed on the device from the FP32
+    fields."""
+    s = rt.Solver(2, shape, stretch, DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"], Ra=1e6, precision=rt.FP32_DEV,
+                  seed=1, noise_amp=1e-6, mass_fix_every=1000)
+    i0 = s.integrals()
+    M0 = i0["volume"] + i0["mass_dev"]
+    worst = 0.0
+    for _ in range(10):
+        s.step(2000)
+        i = s.integrals()
+        worst = max(worst, abs(i["mass_dev"] - i0["mass_dev"]) / M0)
+    print("FP32 mass drift", shape, worst, flush=True)
+    assert worst <= 1e-7, worst
+
+
 # ------------------------------------------------------------- 3D --------
 
 DHC3 = dict(kind=(1, 1, 2, 2, 2, 2), Tdev=(-0.5, 0.5, 0, 0, 0, 0), gaxis=2)
@@ -372,15 +444,17 @@ def test_fp64_3d_cavity_parity(prec):
     assert max(rel) <= FP64_TOL, rel
 
 
+@pytest.mark.timeout(300)
 def test_fp64_3d_48cube_tanh_parity_200_steps():
     """A 48^3 tanh (phi = 1.8) cubic cavity at Ra = 1e5, 200 steps: twelve
-    4x4x4 tiles along each axis, fields within 1e-12.  The oracle
-    needs about a minute."""
+    4x4x4 tiles along each axis, fields within 1e-12 on P14's scale
+    max |oracle|.  The oracle needs about a minute."""
     s, o = make_pair(3, (48, 48, 48), (1.8, 1.8, 1.8), **DHC3, Ra=1e5, noise=1e-3)
     s.step(200)
     o.step(200)
-    rel = field_rel(s, o, 3)
-    print("48^3 tanh, 200 steps: rel", rel, flush=True)
+    rel = field_rel(s, o, 3, Vc=0.0)
+    print("48^3 tanh, 200 steps: rel (P14 scale)", rel, "|u| max",
+          max(np.abs(o.prim(f)).max() for f in (1, 2, 3)), flush=True)
     assert max(rel) <= FP64_TOL, rel
 
 
@@ -462,7 +536,9 @@ def test_tlbfs_fp64_cavity_parity(prec, shape, stretch):
     s, o = make_pair(2, shape, stretch, Ra=1e5, precision=prec, method=rt.METHOD_TLBFS, **DHC2)
     s.step(300)
     o.step(300)
-    assert max(field_rel(s, o, 2)) <= 1e-11
+    rel = field_rel(s, o, 2)
+    print("TLBFS", shape, prec, "rel", rel, flush=True)
+    assert max(rel) <= TLBFS_TOL, rel
 
 
 def test_tlbfs_fp64_periodic_rayleigh_benard_and_random_state():
@@ -471,7 +547,9 @@ def test_tlbfs_fp64_periodic_rayleigh_benard_and_random_state():
                      method=rt.METHOD_TLBFS)
     s.step(400)
     o.step(400)
-    assert max(field_rel(s, o, 2)) <= 1e-11
+    rel = field_rel(s, o, 2)
+    print("TLBFS RB rel", rel, flush=True)
+    assert max(rel) <= TLBFS_TOL, rel
     N = 33 * 21
     kind = (1, 2, 2, 1)
     s, o = make_pair(2, (33, 21), (1.5, 0.0), kind, (0.3, 0.0, 0.0, -0.2), 0, Ra=1e4, method=rt.METHOD_TLBFS,
@@ -481,7 +559,9 @@ def test_tlbfs_fp64_periodic_rayleigh_benard_and_random_state():
     o.set_prim(rho, u, T)
     s.step(50)
     o.step(50)
-    assert max(field_rel(s, o, 2)) <= 1e-11
+    rel = field_rel(s, o, 2)
+    print("TLBFS random state rel", rel, flush=True)
+    assert max(rel) <= TLBFS_TOL, rel
 
 
 @pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP64_DEV])
@@ -490,7 +570,9 @@ def test_tlbfs_fp64_3d_cavity_parity(prec):
                      precision=prec, method=rt.METHOD_TLBFS)
     s.step(150)
     o.step(150)
-    assert max(field_rel(s, o, 3)) <= 1e-11
+    rel = field_rel(s, o, 3)
+    print("TLBFS 3D", prec, "rel", rel, flush=True)
+    assert max(rel) <= TLBFS_TOL, rel
 
 
 def test_tlbfs_two_step_launches_equal_one_step_launches():
