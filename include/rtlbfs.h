@@ -220,6 +220,32 @@ int rtlbfs_set_state(rtlbfs_t h, const double *host_rho, const double *host_u, c
  * form of the handle (for checkpoints and parity checks; synchronising). */
 int rtlbfs_get_stored(rtlbfs_t h, int field, double *host_out, size_t count);
 
+/* Eq. 65 ratios between two states held in caller device memory, with no
+ * handle and no allocation.  For callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.
+ *   dim: 2 or 3; precision: the storage of both states (RTLBFS_FP64_PLAIN,
+ *     RTLBFS_FP32_DEV or RTLBFS_FP64_DEV), float elements for FP32_DEV,
+ *     double otherwise;
+ *   old_state, new_state: device pointers to dim + 2 stored fields each
+ *     (rho or r, rho u_a, rho c_p T or theta), field k of a state starting
+ *     at element k * fstride, cells x-fastest -- the layout of a handle's
+ *     state copy; read only;
+ *   dev_out: device memory for 2 doubles, receives res_u and res_T exactly
+ *     as rtlbfs_residual defines them (new_state at time level n+1), with
+ *     the per-cell terms formed as the step kernels form them;
+ *   hip_stream: stream of the current device (NULL = null stream).
+ * Enqueues two kernels and returns without synchronising.  Allocates
+ * nothing: the block partial sums live in a fixed 32 KiB device array per GPU
+ * (set up by the first call on each device), shared by every call on that
+ * GPU, so calls that overlap on one GPU race; calls ordered on one stream do
+ * not.  EINVAL for a bad dim or precision, NULL pointers, cells < 1 or
+ * above RTLBFS_RESIDUAL_STATES_MAX_CELLS, or fstride < cells; EDEVICE when
+ * a HIP call or launch fails. */
+#define RTLBFS_RESIDUAL_STATES_MAX_CELLS ((int64_t)1 << 31)
+int rtlbfs_residual_states(int dim, int precision, int64_t cells, int64_t fstride, const void *old_state,
+                           const void *new_state, double *dev_out, void *hip_stream);
+
 /* Handle facts (host only, no synchronisation). */
 int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out);
 

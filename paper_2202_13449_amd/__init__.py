@@ -8,4 +8,4 @@ from .rtlbfs import (  # noqa: F401
     METHOD_RTLBFS, METHOD_TLBFS, OK, PERIODIC,
     WALL_ADIABATIC, WALL_ISOTHERMAL, Batch, Curv3Solver, CurvSolver, RtlbfsError, Solver, load_library, make_bc, make_mesh,
     make_opts,
-    mesh_nodes, strerror)
+    mesh_nodes, residual_states, strerror)

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtlbfs.so")
-SOURCES = [os.path.join(CSRC, "rtlbfs_api.hip"), os.path.join(CSRC, "rtlbfs_batch.hip")]
+SOURCES = [os.path.join(CSRC, "rtlbfs_api.hip"), os.path.join(CSRC, "rtlbfs_batch.hip"),
+           os.path.join(CSRC, "rtlbfs_noalloc.hip")]
 HEADERS = ["rtlbfs_device.h", "step2d.h", "step3d.h", "reduce.h", "curv2d.h", "curv_host.h", "curv3d.h", "curv3_host.h"]
 
 

@@ -164,13 +164,14 @@ def load_library() -> C.CDLL:
     lib.rtlbfs_batch_sync.argtypes = [VP]
     lib.rtlbfs_batch_diverged.argtypes = [VP, C.POINTER(C.c_int)]
     lib.rtlbfs_batch_destroy.argtypes = [VP]
+    lib.rtlbfs_residual_states.argtypes = [I, I, I64, I64, VP, VP, VP, VP]
     for name in ("rtlbfs_opts_init", "rtlbfs_mesh_nodes", "rtlbfs_create", "rtlbfs_step", "rtlbfs_sync",
                  "rtlbfs_residual", "rtlbfs_nusselt", "rtlbfs_integrals", "rtlbfs_get_field", "rtlbfs_get_stored",
                  "rtlbfs_set_state", "rtlbfs_get_info", "rtlbfs_destroy", "rtlbfs_curv_create", "rtlbfs_wall_heat",
                  "rtlbfs_curv_cells", "rtlbfs_curv3_create", "rtlbfs_curv3_cells", "rtlbfs_batch_create",
                  "rtlbfs_batch_step",
                  "rtlbfs_batch_nusselt", "rtlbfs_batch_residual", "rtlbfs_batch_get_field", "rtlbfs_batch_get_info",
-                 "rtlbfs_batch_sync", "rtlbfs_batch_diverged", "rtlbfs_batch_destroy"):
+                 "rtlbfs_batch_sync", "rtlbfs_batch_diverged", "rtlbfs_batch_destroy", "rtlbfs_residual_states"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -232,6 +233,29 @@ def _torch_stream_and_alloc(nbytes: int):
     ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
     return ws, stream
+
+
+def residual_states(dim: int, precision: int, cells: int, fstride: int, old_state, new_state, out) -> None:
+    """Eq. 65 ratios between two stored states in device memory (torch
+    tensors in the handle's SoA layout: dim + 2 fields, `fstride` elements
+    apart) into `out` (a float64 device tensor of 2), through
+    rtlbfs_residual_states on torch's current stream.  Allocates nothing."""
+    import torch
+
+    for t in (old_state, new_state, out):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+            raise ValueError("device tensors expected")
+    want = torch.float32 if precision == FP32_DEV else torch.float64
+    if old_state.dtype != want or new_state.dtype != want or out.dtype != torch.float64 or out.numel() < 2:
+        raise ValueError("dtype or size mismatch")
+    if old_state.numel() < (dim + 2) * fstride or new_state.numel() < (dim + 2) * fstride:
+        raise ValueError("state tensors shorter than (dim + 2) * fstride")
+    rc = load_library().rtlbfs_residual_states(dim, precision, int(cells), int(fstride),
+                                                C.c_void_p(old_state.data_ptr()), C.c_void_p(new_state.data_ptr()),
+                                                C.c_void_p(out.data_ptr()),
+                                                C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != OK:
+        raise RtlbfsError(rc, "rtlbfs_residual_states: " + strerror(rc))
 
 
 class Solver:

@@ -321,3 +321,22 @@ def test_meshes_beyond_one_dispatch_are_rejected_before_touching_the_device():
     cm = rtb.CurvMesh()
     cm.n[:] = [1 << 20, 8192]
     assert lib.rtlbfs_curv_workspace_bytes(C.byref(cm), C.byref(o)) == 0
+
+
+def test_residual_states_validates_before_touching_the_device():
+    """The allocation-free Eq. 65 entry point rejects bad arguments (dim,
+    precision, NULL pointers, sizes beyond its documented maximum, a field
+    stride below the cell count) with EINVAL before any HIP call."""
+    lib = rt.load_library()
+    p = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    f = lib.rtlbfs_residual_states
+    assert f(1, rt.FP64_PLAIN, 64, 64, p, p, p, None) == rt.EINVAL
+    assert f(4, rt.FP64_PLAIN, 64, 64, p, p, p, None) == rt.EINVAL
+    assert f(2, 7, 64, 64, p, p, p, None) == rt.EINVAL
+    assert f(2, rt.FP32_DEV, 64, 64, None, p, p, None) == rt.EINVAL
+    assert f(2, rt.FP32_DEV, 64, 64, p, None, p, None) == rt.EINVAL
+    assert f(2, rt.FP32_DEV, 64, 64, p, p, None, None) == rt.EINVAL
+    assert f(2, rt.FP64_DEV, 0, 64, p, p, p, None) == rt.EINVAL
+    assert f(3, rt.FP64_DEV, 100, 99, p, p, p, None) == rt.EINVAL
+    big = (1 << 31) + 1
+    assert f(3, rt.FP64_PLAIN, big, big, p, p, p, None) == rt.EINVAL
