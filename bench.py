@@ -1,16 +1,28 @@
 """Throughput of the RTLBFS time step on one MI355X.
 
-Workload: 2D differentially heated cavity, 256 x 256 tanh-stretched mesh
-(phi = 1.5 on both axes, finest cell = 1), Ra = 1e6, Pr = 0.71, V_c = 0.1,
-hot / cold isothermal side walls, adiabatic top / bottom, fluid at rest with
-seeded 1e-6 temperature noise.  One step is one full RTLBFS time step (face
-lattice predictor, fluxes, divergence, update) with its FP64 reductions at
-their cadence (Eq. 65 residual every 100 steps, mass-drift correction every
-1000 steps), replayed from captured HIP graphs.  `value` is the FP32
-deviation-storage path; the FP64 plain path is timed beside it on the same
-workload.  Inputs are resident in HBM before the timed region starts.
+Headline workload: 2D differentially heated cavity, 256 x 256 tanh-stretched
+mesh (phi = 1.5 on both axes, finest cell = 1), Ra = 1e6, Pr = 0.71,
+V_c = 0.1, hot / cold isothermal side walls, adiabatic top / bottom, fluid
+at rest with seeded 1e-6 temperature noise.  One step is one full RTLBFS
+time step (face lattice predictor, fluxes, divergence, update) with its FP64
+reductions at their cadence (Eq. 65 residual every 100 steps, mass-drift
+correction every 1000 steps), replayed from captured HIP graphs.  `value` is
+the FP32 deviation-storage path over exactly `steps` timed steps; the FP64
+plain path is timed beside it.  Inputs are resident in HBM before each timed
+region starts.
 
-Prints one JSON line.
+The same JSON line carries
+- `roofline`: the dominant kernel's algorithmic rate against the FP32
+  vector peak, its HBM fraction and, while the kernel is unchanged, the
+  HBM traffic the counters measured;
+- `fixed_nu_error`: FP64 run to steady state (both Eq. 65 ratios below
+  1e-8), FP32 run for the same steps, the relative Nusselt differences;
+- `legs`: the 256-cavity batch (FP32 and FP64 batches and the 256
+  problems as separate handles) and the 192^3 cube (FP32 and FP64), each
+  with its HBM and ALU fractions and counter traffic ratio;
+- `cpu_baseline`: the FP64 oracle timed on a bounded sample.
+
+Other workloads are selected with --workload / --batch.
 """
 import argparse
 import math
@@ -38,34 +50,40 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP32_NONPACKED_PEAK_TFLOPS = 78.6
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-# Algorithmic flops per 2D cell-update (additions, multiplications and
-# divisions of one time step, per cell): two faces (428 FP32-deviation / 407
-# FP64-plain each, counted on the library's face function by
-# tests/test_flops_cpu.py) + Eq. 55 gradients 64 (4 primitives x 2 axes x 8)
-# + primitives 5 (4 plain) + area weighting 8 + update and buoyancy 23
-# + the FP32 stochastic rounding of 4 fields 24 (TwoSum, 6 each).
-FLOPS_PER_CELL = {"f32": 2 * 428 + 64 + 5 + 8 + 23 + 24, "f64": 2 * 407 + 64 + 4 + 8 + 23}
+# Algorithmic flops per cell-update: the operation count of one time step of
+# the method in the paper's plain FP64 form, counted on the library's face
+# function with a counting number type (tests/test_flops_cpu.py): 2D, two
+# faces of 407 + Eq. 55 gradients 64 (4 primitives x 2 axes x 8) + primitives
+# 4 + area weighting 8 + update and buoyancy 23 = 913; 3D, three faces of 840
+# + gradients 120 + primitives, weighting and update about 30 = 2670.  The
+# deviation storage adds 21 per 2D face (31 in 3D) and the FP32 stochastic
+# rounding 6 per stored field; both are implementation overhead and are not
+# counted.
+ALG_FLOPS_PER_CELL = {2: 2 * 407 + 64 + 4 + 8 + 23, 3: 3 * 840 + 120 + 30}
+BYTES_PER_CELL_3D = {"f32": 5 * 4 * 2, "f64": 5 * 8 * 2}
 CSRC = os.path.join(ROOT, "paper_2202_13449_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step2d_fp32_cavity256.json")
+TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_k_batch_step2d_256cavities.json")
+TRAFFIC_FILE_3D = os.path.join(ROOT, "profiles", "traffic_k_step3d_cube192.json")
 
 
-def kernel_sources_sha256() -> str:
-    """Hash of what defines the 2D step kernel (its device headers, its
-    __global__ wrapper and the compile flags of build.py), so stored counter
-    data is used only while that kernel is unchanged."""
+def sources_sha256(headers, api_file, kernel) -> str:
+    """Hash of what defines one step kernel (its device headers, its
+    __global__ wrapper in `api_file` and the compile flags of build.py), so
+    stored counter data is used only while that kernel is unchanged."""
     import hashlib
     import re
 
     h = hashlib.sha256()
-    for name in ("rtlbfs_device.h", "step2d.h"):
+    for name in headers:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
-    with open(os.path.join(CSRC, "rtlbfs_api.hip")) as f:
+    with open(os.path.join(CSRC, api_file)) as f:
         api = f.read()
-    m = re.search(r"template <[^\n]*>\n__global__[^\n]*k_step2d\(.*?\n}\n", api, re.S)
+    m = re.search(r"template <[^\n]*>\n__global__[^\n]*" + kernel + r"\(.*?\n}\n", api, re.S)
     if not m:
-        raise RuntimeError("k_step2d wrapper not found in rtlbfs_api.hip")
-    h.update(b"k_step2d\0" + m.group(0).encode())
+        raise RuntimeError(f"{kernel} wrapper not found in {api_file}")
+    h.update(kernel.encode() + b"\0" + m.group(0).encode())
     with open(os.path.join(ROOT, "paper_2202_13449_amd", "build.py")) as f:
         build = f.read()
     fm = re.search(r"flags = \[.*?\]", build, re.S)  # the code-generation flags, not the file lists
@@ -75,21 +93,37 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(tile):
-    """HBM bytes per launch of the dominant kernel (launch shape `tile` = tile
-    x, tile y, steps per launch) from the
-    committed counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its
-    copy-kernel calibration); None when the kernels changed since it was
-    taken."""
+def kernel_sources_sha256() -> str:
+    return sources_sha256(("rtlbfs_device.h", "step2d.h"), "rtlbfs_api.hip", "k_step2d")
+
+
+def batch_sources_sha256() -> str:
+    return sources_sha256(("rtlbfs_device.h", "step2d.h"), "rtlbfs_batch.hip", "k_batch_step2d")
+
+
+def cube_sources_sha256() -> str:
+    return sources_sha256(("rtlbfs_device.h", "step3d.h"), "rtlbfs_api.hip", "k_step3d")
+
+
+def stored_traffic(path, sha, key):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by its
+    copy-kernel calibration) from a committed counter summary; None when the
+    kernel changed since the counters were taken or no entry exists."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sources_sha256") != kernel_sources_sha256():
+    if t.get("kernel_sources_sha256") != sha:
         return None
-    key = f"{tile[0]}x{tile[1]}" + ("" if tile[2] == 1 else f"/{tile[2]}")
     return t.get("bytes_per_launch_by_tile", {}).get(key)
+
+
+def measured_traffic(tile):
+    """Traffic of the 2D step kernel in launch shape `tile` (tile x, tile y,
+    steps per launch)."""
+    key = f"{tile[0]}x{tile[1]}" + ("" if tile[2] == 1 else f"/{tile[2]}")
+    return stored_traffic(TRAFFIC_FILE, kernel_sources_sha256(), key)
 
 
 # opts.tile of each 2D launch shape (tile x, tile y, steps per launch)
@@ -234,6 +268,49 @@ def batch_bench(rt, torch, steps, warmup, sequential=True):
     return out
 
 
+def batch_steady_bench(rt, torch, steps, warmup, total=200_000, chunk=10_000, tol=1e-8):
+    """The fixed-Nu-error check of the 256-cavity batch: FP64 plain and FP32
+    deviation batches advanced together in chunks to `total` steps; members
+    whose FP64 Eq. 65 ratios are both below `tol` are steady, and for them
+    the FP32 Nusselt numbers are compared with FP64.  Progress goes to
+    stderr after every chunk."""
+    from paper_2202_13449_amd.workloads import (CAVITY_GRAVITY, CAVITY_KIND, CAVITY_TDEV, batch_cavities,
+                                                total_cells)
+
+    members = batch_cavities()
+    meshes = [rt.make_mesh(2, (m["n"], m["n"]), (m["stretch"], m["stretch"])) for m in members]
+    bcs = [rt.make_bc(CAVITY_KIND, CAVITY_TDEV, CAVITY_GRAVITY) for _ in members]
+    kw = dict(Ma=MA, seed=4, noise_amp=1e-6, residual_every=1000)
+    b64 = rt.Batch(meshes, [m["Ra"] for m in members], [m["Pr"] for m in members], bcs, precision=rt.FP64_PLAIN,
+                   **kw)
+    b32 = rt.Batch(meshes, [m["Ra"] for m in members], [m["Pr"] for m in members], bcs, precision=rt.FP32_DEV,
+                   mass_fix_every=1000, **kw)
+    done = 0
+    t0 = time.perf_counter()
+    while done < total:
+        b64.step(chunk)
+        b32.step(chunk)
+        b32.sync()
+        done += chunk
+        res = b64.residuals()
+        print(f"batch steady: {done} steps, {int((res.max(axis=1) < tol).sum())} of {len(members)} FP64 members "
+              f"below {tol:g}, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    res64 = b64.residuals()
+    steady = [k for k in range(len(members)) if max(res64[k]) < tol]
+    rows = []
+    for k in steady:
+        a, c = b32.nusselt(k), b64.nusselt(k)
+        rows.append({"member": k, "n": members[k]["n"], "stretch": members[k]["stretch"], "Ra": members[k]["Ra"],
+                     "Pr": members[k]["Pr"], "nu_fp64": c, "fp64_residual": list(res64[k]),
+                     "nu_rel_diff": {q: abs(a[q] - c[q]) / abs(c[q]) for q in c}})
+    worst = max((max(r["nu_rel_diff"].values()) for r in rows), default=None)
+    return {"workload": "256 batched cavities, FP32 vs FP64 at steady state", "cells": total_cells(members),
+            "steps": done, "tol": tol, "steady_members": len(steady), "members": len(members),
+            "max_nu_rel_diff_steady": worst,
+            "members_above_1e-4": int(sum(max(r["nu_rel_diff"].values()) > 1e-4 for r in rows)),
+            "rows": rows, "seconds": time.perf_counter() - t0}
+
+
 def timed(torch, solver, steps):
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -246,38 +323,65 @@ def timed(torch, solver, steps):
     return e0.elapsed_time(e1) / steps
 
 
-RB_TOTAL_STEPS, RB_AVG_STEPS, RB_SAMPLE_EVERY = 200_000, 50_000, 1_000
+# C3: the stability test is 200,000 steps; the run then continues so the
+# time averages have a stated statistical error.  Samples every 100 steps
+# resolve the box's acoustic period (2 H / c_s, about 3,500 steps for
+# H = 512, and its harmonics), which sampling every 1,000 steps aliased.
+RB_PASS_STEPS, RB_TOTAL_STEPS, RB_AVG_STEPS, RB_SAMPLE_EVERY, RB_BLOCKS = 200_000, 1_200_000, 1_000_000, 100, 20
+
+
+def batch_means(x, blocks):
+    """Mean and its standard error from `blocks` contiguous block means (the
+    blocks are long against the correlation time of the samples)."""
+    x = np.asarray(x, dtype=np.float64)
+    m = len(x) // blocks
+    bm = x[:m * blocks].reshape(blocks, m).mean(axis=1)
+    return float(bm.mean()), float(bm.std(ddof=1) / math.sqrt(blocks))
 
 
 def rb_bench(rt, torch, steps, warmup):
     """1024 x 512 Rayleigh-Benard box, periodic in x, Ra = 1e8 on H = 512,
     conduction profile plus 1e-3 seeded noise, FP32 deviation storage: the
-    throughput over `steps`, then the run continued to 200,000 steps with the
-    wall and volume Nusselt numbers averaged over the last 50,000 (sampled
-    every 1,000 steps), max |u| and finiteness at the end."""
+    throughput over `steps`; the stability criterion at 200,000 steps
+    (finite, max |u| < 0.3); then the run continued to 1.2M steps with the
+    wall and volume (Eq. 69 along the vertical) Nusselt numbers sampled
+    every 100 steps over the last 1M, as means with batch-means standard
+    errors."""
     s = rt.Solver(2, (1024, 512), (0, 0), (0, 0, 1, 1), (0, 0, 0.5, -0.5), 1, Ra=1e8, Pr=0.71, Ma=MA,
                   precision=rt.FP32_DEV, init=rt.INIT_CONDUCTION, seed=3, noise_amp=1e-3)
     s.step(warmup)
     ms = timed(torch, s, steps)
     done = warmup + steps
-    samples = []
-    while done < RB_TOTAL_STEPS:
-        k = min(RB_SAMPLE_EVERY - done % RB_SAMPLE_EVERY, RB_TOTAL_STEPS - done)
-        s.step(k)
-        done += k
-        if done % RB_SAMPLE_EVERY == 0 and done > RB_TOTAL_STEPS - RB_AVG_STEPS:
-            samples.append(s.nusselt())
+    s.step(RB_PASS_STEPS - done)
+    done = RB_PASS_STEPS
     s.sync()
     u, v = s.field(1), s.field(2)
     umax = float(np.sqrt(u * u + v * v).max())
+    keys = ("hot_avg", "cold_avg", "volume")
+    samples = {k: [] for k in keys}
+    t0 = time.perf_counter()
+    while done < RB_TOTAL_STEPS:
+        s.step(RB_SAMPLE_EVERY)
+        done += RB_SAMPLE_EVERY
+        if done > RB_TOTAL_STEPS - RB_AVG_STEPS:
+            nu = s.nusselt()
+            for k in keys:
+                samples[k].append(nu[k])
+    s.sync()
+    u2, v2 = s.field(1), s.field(2)
+    stats = {}
+    for k in keys:
+        m, se = batch_means(samples[k], RB_BLOCKS)
+        stats[k] = {"mean": m, "stderr": se, "std": float(np.std(samples[k]))}
     cells = 1024 * 512
-    avg = {k: float(np.mean([x[k] for x in samples])) for k in ("hot_avg", "cold_avg", "volume")} if samples else {}
     return {"workload": "rb1024x512 Ra=1e8 FP32", "cells": cells, "steps_timed": steps, "ms_per_step": ms,
             "value": cells / (ms * 1e-3), "hbm_gbs": BYTES_PER_CELL["f32"] * cells / (ms * 1e-3) / 1e9,
-            "total_steps": done, "finite": bool(np.isfinite(umax)), "umax": umax,
+            "pass_steps": RB_PASS_STEPS, "finite": bool(np.isfinite(umax)), "umax": umax,
             "pass": bool(np.isfinite(umax) and umax < 0.3),
-            "nu_time_avg_last_50k": avg, "nu_samples": len(samples), "nu_final": s.nusselt(),
-            "tile": list(launch_shape(s.info))}
+            "total_steps": done, "umax_end": float(np.sqrt(u2 * u2 + v2 * v2).max()),
+            "nu_time_avg": stats, "nu_samples": len(samples["volume"]), "sample_every": RB_SAMPLE_EVERY,
+            "avg_window_steps": RB_AVG_STEPS, "batch_means_blocks": RB_BLOCKS,
+            "seconds_sampling": time.perf_counter() - t0, "tile": list(launch_shape(s.info))}
 
 
 def cube_bench(rt, torch, steps, warmup):
@@ -382,6 +486,90 @@ def cube_table5_bench(rt, torch, steps, warmup, n=80, chunk=20_000, tol=2e-5):
         print(json.dumps({f"Ra={Ra:g}": out["cases"][f"{Ra:g}"]}), flush=True)
         del s
         torch.cuda.empty_cache()
+    return out
+
+
+def cube_solver(rt, n, prec, **kw):
+    return rt.Solver(3, (n, n, n), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=1e6,
+                     Pr=0.71, Ma=MA, precision=prec, seed=1, noise_amp=1e-6, **kw)
+
+
+def cube_steady_bench(rt, torch, steps, warmup, n=192, coarse=80, chunk=20_000, tol=1e-8, coarse_tol=1e-6,
+                      budget_s=560.0):
+    """C5's fixed-Nu-error check: the 192^3 cube at Ra = 1e6 in FP64 plain
+    and FP32 deviation at steady state.  To reach it within one run, both
+    start from the same state: the 80^3 FP64 steady solution (hot-wall Nu
+    changing by less than coarse_tol per chunk) interpolated trilinearly in
+    the normalised coordinate onto the 192^3 cell centres (rho, u, T; lattice
+    units scale with the mesh, u / V_c and rho - 1 do not).  The steady state
+    does not depend on the start, only the transient is shortened.  FP64
+    then runs until both Eq. 65 ratios fall below tol or budget_s runs out;
+    FP32 runs the same number of steps.  Progress goes to stderr."""
+    from scipy.interpolate import RegularGridInterpolator
+
+    t0 = time.perf_counter()
+    c = cube_solver(rt, coarse, rt.FP64_PLAIN, residual_every=1000)
+    done, prev = 0, None
+    while done < 2_000_000:
+        c.step(chunk)
+        done += chunk
+        nu = c.nusselt()["hot_avg"]
+        if prev is not None and abs(nu - prev) < coarse_tol * nu:
+            break
+        prev = nu
+    print(f"cube steady: {coarse}^3 FP64 {done} steps, Nu hot {nu:.6f}, residual {c.residual()}, "
+          f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    xc_c, Lc = rt.mesh_nodes(coarse, 1.8)
+    xf, Lf = rt.mesh_nodes(n, 1.8)
+    gc = 0.5 * (xc_c[1:] + xc_c[:-1]) / Lc
+    gf = 0.5 * (xf[1:] + xf[:-1]) / Lf
+    Z, Y, X = np.meshgrid(gf, gf, gf, indexing="ij")
+    pts = np.stack([Z.ravel(), Y.ravel(), X.ravel()], axis=1)
+    del Z, Y, X
+    fields = []
+    for f in range(5):
+        g = c.field(f).reshape(coarse, coarse, coarse)
+        fields.append(RegularGridInterpolator((gc, gc, gc), g, bounds_error=False, fill_value=None)(pts))
+    del pts, c
+    torch.cuda.empty_cache()
+    rho, u, T = fields[0], np.concatenate(fields[1:4]), fields[4]
+    s64 = cube_solver(rt, n, rt.FP64_PLAIN, residual_every=1000)
+    s32 = cube_solver(rt, n, rt.FP32_DEV, residual_every=1000)
+    s64.set_state(rho, u, T)
+    s32.set_state(rho, u, T)
+    del fields, rho, u, T
+    t1 = time.perf_counter()
+    done = 0
+    while True:
+        s64.step(chunk)
+        done += chunk
+        r = s64.residual()
+        print(f"cube steady: 192^3 FP64 {done} steps, residual {r}, Nu hot {s64.nusselt()['hot_avg']:.7f}, "
+              f"{time.perf_counter() - t1:.0f} s", file=sys.stderr, flush=True)
+        if max(r) < tol or time.perf_counter() - t1 > budget_s:
+            break
+    t64 = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    left = done
+    while left > 0:
+        k = min(chunk * 5, left)
+        s32.step(k)
+        s32.sync()
+        left -= k
+        print(f"cube steady: 192^3 FP32 {done - left} steps, {time.perf_counter() - t2:.0f} s", file=sys.stderr,
+              flush=True)
+    a, b = s32.nusselt(), s64.nusselt()
+    diff = {k: abs(a[k] - b[k]) / abs(b[k]) for k in b}
+    out = {"workload": "cube192 tanh1.8 Ra=1e6, FP32 vs FP64 at steady state", "coarse_start": coarse,
+           "steps": done, "steady": bool(max(s64.residual()) < tol), "fp64_residual": list(s64.residual()),
+           "fp32_residual": list(s32.residual()), "nu_fp64": b, "nu_fp32": a, "nu_rel_diff": diff,
+           "max_nu_rel_diff": max(diff.values()), "seconds_fp64": t64, "seconds_fp32": time.perf_counter() - t2}
+    for name, x in (("fp64", s64), ("fp32", s32)):
+        u = x.field(1).reshape(n, n, n)
+        w = x.field(3).reshape(n, n, n)
+        h = n // 2
+        out[f"{name}_u_max_over_Vc"] = float(u[:, h - 1:h + 1, h - 1:h + 1].mean(axis=(1, 2)).max() / MA)
+        out[f"{name}_w_max_over_Vc"] = float(w[h - 1:h + 1, h - 1:h + 1, :].mean(axis=(0, 1)).max() / MA)
     return out
 
 
@@ -866,6 +1054,166 @@ def annulus_table7_bench(rt, torch, steps, warmup, chunk=100_000, max_steps=1_50
     return {"workload": "annulus Table 7 (Ar=2, eta=2, Pr=0.71, 120x1x240 wedge), FP32 deviation", "rows": rows}
 
 
+def rates(cells, ms, dim, prec):
+    """Algorithmic HBM and ALU rates of one step over `cells` in `ms`."""
+    bpc = (BYTES_PER_CELL if dim == 2 else BYTES_PER_CELL_3D)[prec]
+    gbs = bpc * cells / (ms * 1e-3) / 1e9
+    tf = ALG_FLOPS_PER_CELL[dim] * cells / (ms * 1e-3) / 1e12
+    peak = FP32_VECTOR_PEAK_TFLOPS if prec == "f32" else FP64_VECTOR_PEAK_TFLOPS
+    out = {"ms_per_step": ms, "value": cells / (ms * 1e-3), "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+           "alu_tflops": tf, "alu_frac": tf / peak}
+    if prec == "f32":
+        out["alu_frac_nonpacked"] = tf / FP32_NONPACKED_PEAK_TFLOPS
+    return out
+
+
+def headline(rt, torch, args):
+    """The 256^2 tanh cavity: FP32 deviation (`value`) and FP64 plain, each
+    over exactly `steps` timed steps; the dominant kernel's launch time for
+    the roofline."""
+    cells = N_CELLS_SIDE * N_CELLS_SIDE
+    r32 = time_path(rt, torch, rt.FP32_DEV, args.steps, args.warmup)
+    ms32 = r32["event_ms"] / args.steps
+    out = {
+        "metric": "cell-updates/s",
+        "value": cells / (ms32 * 1e-3),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D differentially heated cavity 256x256 tanh (phi=1.5) Ra=1e6 Pr=0.71 "
+                               "FP32 deviation storage, FP64 reductions",
+                   "cells": cells, "residual_every": 100, "mass_fix_every": 1000},
+    }
+    # Dominant kernel: the FP32 step kernel.  Its algorithmic intensity is
+    # 913 flop / 32 B = 29 flop/B, above the FP32 ridge (157.3 / 8 = 20), so
+    # the vector ALU roofline is the lower one; the metric's HBM fraction is
+    # reported beside it (hbm_frac).
+    tile32 = launch_shape(r32["solver"].info)
+    kms, ktile = time_step_kernel(rt, torch, rt.FP32_DEV, args.steps, args.warmup, TILES_2D[tile32])
+    k = rates(cells, kms, 2, "f32")
+    out["roofline"] = {"bound": "alu", "achieved": k["alu_tflops"], "peak": FP32_VECTOR_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": k["alu_frac"], "traffic": measured_traffic(ktile),
+                       "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS, "frac_nonpacked": k["alu_frac_nonpacked"],
+                       "kernel": "k_step2d<float, deviation>", "kernel_us": kms * 1e3, "kernel_tile": ktile,
+                       "steps_per_launch": ktile[2], "launch_us": kms * 1e3 * ktile[2],
+                       "flops_per_cell": ALG_FLOPS_PER_CELL[2], "bytes_per_cell": BYTES_PER_CELL["f32"],
+                       "hbm_achieved_gbs": k["hbm_gbs"], "hbm_frac": k["hbm_frac"]}
+    out["hbm_roofline_frac"] = k["hbm_frac"]
+    out["nu_fp32"] = r32["nu"]
+    out["tile"] = list(tile32)
+    if not args.fp32_only:
+        r64 = time_path(rt, torch, rt.FP64_PLAIN, args.steps, args.warmup)
+        ms64 = r64["event_ms"] / args.steps
+        out["fp64_plain"] = rates(cells, ms64, 2, "f64")
+        out["speedup_fp32_vs_fp64"] = ms64 / ms32
+    return out
+
+
+def steady_nu_error(rt, tol=1e-8, max_steps=4_000_000, chunk=20_000):
+    """The fixed-Nu-error check on the benchmark workload: FP64 plain run
+    until both Eq. 65 ratios are below `tol` (steady state), FP32 deviation
+    run for the same number of steps; relative Nusselt differences, the
+    Table 1 velocity maxima of both and the FP32 field errors."""
+    s64 = make_solver(rt, rt.FP64_PLAIN)
+    n = 0
+    t0 = time.perf_counter()
+    while n < max_steps:
+        s64.step(chunk)
+        n += chunk
+        if max(s64.residual()) < tol:
+            break
+    t64 = time.perf_counter() - t0
+    s32 = make_solver(rt, rt.FP32_DEV)
+    t0 = time.perf_counter()
+    s32.step(n)
+    s32.sync()
+    t32 = time.perf_counter() - t0
+    a, b = s32.nusselt(), s64.nusselt()
+    return {"steps": n, "steady": bool(max(s64.residual()) < tol), "fp64_residual": list(s64.residual()),
+            "fp32_residual": list(s32.residual()), "nu_fp64": b, "nu_fp32": a,
+            "nu_rel_diff_fp32_vs_fp64": {k: abs(a[k] - b[k]) / abs(b[k]) for k in b},
+            "max_nu_rel_diff": max(abs(a[k] - b[k]) / abs(b[k]) for k in b),
+            "fields_fp32_vs_fp64": field_comparison(s32, s64), "seconds_fp64": t64, "seconds_fp32": t32}
+
+
+def batch_leg(rt, torch, steps, warmup):
+    """The 256 seeded cavities (about 2.3e7 cells) in one launch per step:
+    FP32 deviation and FP64 plain batches, and the same 256 problems as
+    separate FP32 handles stepped one after another."""
+    from paper_2202_13449_amd.workloads import (CAVITY_GRAVITY, CAVITY_KIND, CAVITY_TDEV, batch_cavities,
+                                                total_cells)
+
+    members = batch_cavities()
+    cells = total_cells(members)
+    meshes = [rt.make_mesh(2, (m["n"], m["n"]), (m["stretch"], m["stretch"])) for m in members]
+    bcs = [rt.make_bc(CAVITY_KIND, CAVITY_TDEV, CAVITY_GRAVITY) for _ in members]
+    nsteps = max(steps, 200)
+    out = {"workload": "256 batched 2D cavities (seed 4): sides 64-512, Ra 1e3-1e7, Pr 0.71/7, uniform or tanh",
+           "cells": cells, "steps": nsteps}
+    for name, prec, tag in (("fp32_dev", rt.FP32_DEV, "f32"), ("fp64_plain", rt.FP64_PLAIN, "f64")):
+        b = rt.Batch(meshes, [m["Ra"] for m in members], [m["Pr"] for m in members], bcs, Ma=MA, precision=prec,
+                     seed=4, noise_amp=1e-6, residual_every=100, mass_fix_every=1000)
+        b.step(max(warmup, 20))
+        b.sync()
+        ms = timed(torch, b, nsteps)
+        out[name] = rates(cells, ms, 2, tag)
+        del b
+        torch.cuda.empty_cache()
+    t = stored_traffic(TRAFFIC_FILE_BATCH, batch_sources_sha256(), "16x8")
+    out["fp32_dev"]["traffic"] = t
+    out["fp32_dev"]["traffic_ratio"] = (t / (BYTES_PER_CELL["f32"] * cells)) if t else None
+    out["speedup_fp32_vs_fp64"] = out["fp64_plain"]["ms_per_step"] / out["fp32_dev"]["ms_per_step"]
+    singles = [rt.Solver(2, (m["n"], m["n"]), (m["stretch"], m["stretch"]), CAVITY_KIND, CAVITY_TDEV,
+                         CAVITY_GRAVITY, Ra=m["Ra"], Pr=m["Pr"], Ma=MA, precision=rt.FP32_DEV, seed=4,
+                         noise_amp=1e-6, residual_every=100, mass_fix_every=1000) for m in members]
+    for x in singles:
+        x.step(100)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for x in singles:
+        x.step(100)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1) / 100
+    out["sequential_256_handles_fp32"] = {"ms_per_step": ms_seq, "value": cells / (ms_seq * 1e-3)}
+    out["speedup_batched_vs_sequential"] = ms_seq / out["fp32_dev"]["ms_per_step"]
+    del singles
+    torch.cuda.empty_cache()
+    return out
+
+
+def cube_leg(rt, torch, steps, warmup):
+    """192^3 tanh (phi = 1.8) cubic cavity at Ra = 1e6, FP32 deviation and
+    FP64 plain."""
+    cells = 192 ** 3
+    nsteps = max(steps, 50)
+    out = {"workload": "3D differentially heated cube 192^3 tanh (phi=1.8) Ra=1e6 Pr=0.71", "cells": cells,
+           "steps": nsteps}
+    for name, prec, tag in (("fp32_dev", rt.FP32_DEV, "f32"), ("fp64_plain", rt.FP64_PLAIN, "f64")):
+        s = rt.Solver(3, (192, 192, 192), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=1e6,
+                      Pr=0.71, Ma=MA, precision=prec, seed=1, noise_amp=1e-6)
+        s.step(max(warmup, 10))
+        s.sync()
+        ms = timed(torch, s, nsteps)
+        out[name] = rates(cells, ms, 3, tag)
+        t = stored_traffic(TRAFFIC_FILE_3D, cube_sources_sha256(), tag)
+        out[name]["traffic"] = t
+        out[name]["traffic_ratio"] = (t / (BYTES_PER_CELL_3D[tag] * cells)) if t else None
+        del s
+        torch.cuda.empty_cache()
+    out["speedup_fp32_vs_fp64"] = out["fp64_plain"]["ms_per_step"] / out["fp32_dev"]["ms_per_step"]
+    return out
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle, as written, on a bounded sample of the same workload."""
     from oracle import Oracle, OracleConfig, physics_from_ra, mesh_nodes
@@ -899,7 +1247,7 @@ def main():
                     help="with --batch: skip the 256 single-domain handles (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
-    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "steady256", "cube80", "hill", "methods",
+    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "cube192_steady", "steady256", "cube80", "hill", "methods",
                                                            "stability", "cylinder", "cylinder_table4", "annulus", "annulus_table7",
                                                            "dhc_highra"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
@@ -916,6 +1264,9 @@ def main():
     ap.add_argument("--ra", type=float, default=None,
                     help="dhc_highra (1e7 or 1e8) and cube80 (1e3 ... 1e6): run only this Rayleigh number")
     ap.add_argument("--budget-s", type=float, default=None, help="dhc_highra: wall-clock seconds per case")
+    ap.add_argument("--steady-steps", type=int, default=0,
+                    help="with --batch: advance FP64 and FP32 batches this many steps and compare the Nusselt "
+                         "numbers of the members that reached steady state")
     args = ap.parse_args()
     global HIGHRA_CASES, HIGHRA_BUDGET_S, CUBE80_CASES
     if args.ra is not None:
@@ -949,74 +1300,29 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
         return
     if args.batch:
+        if args.steady_steps:
+            print(json.dumps(batch_steady_bench(rt, torch, args.steps, args.warmup, total=args.steady_steps)),
+                  flush=True)
+            return
         print(json.dumps(batch_bench(rt, torch, args.steps, args.warmup, sequential=not args.no_sequential)),
               flush=True)
         return
     if args.workload != "cavity256":
-        fn = {"rb1024": rb_bench, "cube192": cube_bench, "steady256": steady_bench,
+        fn = {"rb1024": rb_bench, "cube192": cube_bench, "cube192_steady": cube_steady_bench, "steady256": steady_bench,
               "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench,
               "stability": stability_bench, "cylinder": cylinder_bench,
               "cylinder_table4": cylinder_table4_bench, "annulus": annulus_bench,
               "annulus_table7": annulus_table7_bench, "dhc_highra": dhc_highra_bench}[args.workload]
         print(json.dumps(fn(rt, torch, args.steps, args.warmup)), flush=True)
         return
-    cells = N_CELLS_SIDE * N_CELLS_SIDE
-    r32 = time_path(rt, torch, rt.FP32_DEV, args.steps, args.warmup)
-    ms32 = r32["event_ms"] / args.steps
-    value = cells / (ms32 * 1e-3)
-    out = {
-        "metric": "cell-updates/s",
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms32,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "2D differentially heated cavity 256x256 tanh (phi=1.5) Ra=1e6 Pr=0.71 "
-                               "FP32 deviation storage, FP64 reductions",
-                   "cells": cells, "residual_every": 100, "mass_fix_every": 1000},
-    }
-    # Dominant kernel: the FP32 step kernel, one launch per step.  It is
-    # bound by vector ALU work (about 30 flop per algorithmic byte), so the
-    # roofline is the FP32 vector peak; the HBM fraction is reported beside it.
-    fpl = FLOPS_PER_CELL["f32"] * cells   # algorithmic flops per step-kernel launch
-    bpl = BYTES_PER_CELL["f32"] * cells   # algorithmic bytes per step-kernel launch
-    tile32 = launch_shape(r32["solver"].info)
-    kms, ktile = time_step_kernel(rt, torch, rt.FP32_DEV, args.steps, args.warmup, TILES_2D[tile32])
-    achieved = fpl / (kms * 1e-3) / 1e12
-    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(ktile),
-                       "peak_nonpacked": FP32_NONPACKED_PEAK_TFLOPS,
-                       "frac_nonpacked": achieved / FP32_NONPACKED_PEAK_TFLOPS,
-                       "kernel": "k_step2d<float, deviation>", "kernel_us": kms * 1e3, "kernel_tile": ktile,
-                       "steps_per_launch": ktile[2], "launch_us": kms * 1e3 * ktile[2],
-                       "flops_per_cell": FLOPS_PER_CELL["f32"], "bytes_per_cell": BYTES_PER_CELL["f32"],
-                       "hbm_achieved_gbs": bpl / (kms * 1e-3) / 1e9,
-                       "hbm_frac": bpl / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    out["nu_fp32"] = r32["nu"]
-    out["tile"] = list(launch_shape(r32["solver"].info))
+    out = headline(rt, torch, args)
     if not args.fp32_only:
-        r64 = time_path(rt, torch, rt.FP64_PLAIN, args.steps, args.warmup)
-        ms64 = r64["event_ms"] / args.steps
-        out["fp64_plain"] = {"value": cells / (ms64 * 1e-3), "ms_per_step": ms64,
-                             "hbm_gbs": BYTES_PER_CELL["f64"] * cells / (ms64 * 1e-3) / 1e9,
-                             "tflops": FLOPS_PER_CELL["f64"] * cells / (ms64 * 1e-3) / 1e12,
-                             "fp64_frac": FLOPS_PER_CELL["f64"] * cells / (ms64 * 1e-3) / 1e12
-                             / FP64_VECTOR_PEAK_TFLOPS,
-                             "nu": r64["nu"]}
-        out["nu_rel_diff_fp32_vs_fp64"] = {k: abs(r32["nu"][k] - r64["nu"][k]) / abs(r64["nu"][k])
-                                           for k in r64["nu"]}
-        out["speedup_fp32_vs_fp64"] = ms64 / ms32
-        out["fields_fp32_vs_fp64"] = field_comparison(r32["solver"], r64["solver"])
+        out["fixed_nu_error"] = steady_nu_error(rt)
+        out["legs"] = {"batched_256_cavities": batch_leg(rt, torch, args.steps, args.warmup),
+                       "cube192": cube_leg(rt, torch, args.steps, args.warmup)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()
