@@ -111,7 +111,12 @@ typedef struct {
                              live state); 1..5 -> one step per launch on 32x8, 16x16, 64x4, 16x8,
                              8x8 cells; 6..9 -> two steps per launch on 16x16, 32x8, 16x8, 8x8
                              (the state of the first step stays on chip; an odd last step uses
-                             the one-step shape of the same tile) */
+                             the one-step shape of the same tile).
+                             3D launch shape: 0 or 1 -> 4x4x4 cell tiles; 2..5 -> 16x8 columns
+                             marching through segments of 32, 48, 64, 96 planes along z; 6 -> 8x8
+                             columns, segments of 48 planes.  The columns compute each face once
+                             per segment; they agree with the tiles to rounding (FMA contraction
+                             differs between the two kernels), not bit for bit. */
     int round_nearest;    /* FP32_DEV only. 0 (default): the state update u + du is rounded
                              stochastically (unbiased; random bits from a hash of cell, field and a
                              device step counter, reproducible); 1: round-to-nearest, which stalls
@@ -138,7 +143,8 @@ typedef struct {
     double dtl, dt;
     double length[3];           /* domain length per axis */
     int precision;
-    int tile_x, tile_y, tile_z; /* tile the step kernel runs with */
+    int tile_x, tile_y, tile_z; /* tile the step kernel runs with (3D columns: tile_z is the
+                                   segment length) */
     double tune_ms[16];         /* autotuner: ms per step of each 2D launch shape, in opts.tile order
                                    (0 if not timed) */
     int steps_per_launch;       /* time steps one launch of the step kernel advances (1 or 2) */

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtlbfs.so")
 SOURCES = [os.path.join(CSRC, "rtlbfs_api.hip"), os.path.join(CSRC, "rtlbfs_batch.hip"),
            os.path.join(CSRC, "rtlbfs_noalloc.hip")]
-HEADERS = ["rtlbfs_device.h", "step2d.h", "step3d.h", "reduce.h", "curv2d.h", "curv_host.h", "curv3d.h", "curv3_host.h"]
+HEADERS = ["rtlbfs_device.h", "step2d.h", "step3d.h", "step3d_march.h", "reduce.h", "curv2d.h", "curv_host.h", "curv3d.h", "curv3_host.h"]
 
 
 def hipcc() -> str:

@@ -16,6 +16,7 @@
 #include "rtlbfs_device.h"
 #include "step2d.h"
 #include "step3d.h"
+#include "step3d_march.h"
 #include "host_common.h"
 #include "curv2d.h"
 #include "curv_host.h"
@@ -81,6 +82,23 @@ __global__ void __launch_bounds__((curv_threads<TX, TY>())) k_curv_step(Domain d
 
 namespace {
 
+// The column kernel: a TX x TY column marching through planes [z0, z0 + sz).
+// FP32 targets five wavefronts per SIMD (three 16 x 8 blocks of seven per
+// CU, about 47 KB of LDS each); FP64 needs twice the LDS and fits one block.
+template <typename R, bool DEV, int TX, int TY, bool RES, bool TL>
+__global__ void __launch_bounds__((col3_threads<TX, TY>())) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2, 8))) k_step3d_col(Domain d, const R *__restrict__ Uin, R *__restrict__ Uout,
+                                                double *__restrict__ parts, const uint32_t *__restrict__ ctr_in,
+                                                uint32_t *__restrict__ ctr_out, int sz) {
+    const uint32_t key = *ctr_in;
+    // columns x-fastest, then segments; each XCD takes a contiguous band (see xcd_tile)
+    const int ntx = (d.n[0] + TX - 1) / TX, nty = (d.n[1] + TY - 1) / TY;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = t % ntx, by = (t / ntx) % nty, bs = t / (ntx * nty);
+    const int z0 = bs * sz, z1 = min(z0 + sz, d.n[2]);
+    column_step_3d<R, DEV, TX, TY, RES, TL>(d, bx * TX, by * TY, z0, z1, Uin, Uout, parts + (int64_t)t * kPartials, key);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_out = key + 1u;
+}
+
 // 2D launch shapes the autotuner chooses from (opts.tile = index + 1): tile
 // size, time steps per launch, and the one-step shape of the same tile (used
 // for an odd last step).
@@ -100,6 +118,33 @@ static_assert(sizeof(kTiles2Threads) / sizeof(kTiles2Threads[0]) == kNumTiles2, 
 // ~30 KB of LDS and 96 VGPRs leave room for five blocks (20 wavefronts) per
 // CU, where the 8 x 4 x 4 tile's eight wavefronts fit twice (16).
 constexpr int kTX3 = 4, kTY3 = 4, kTZ3 = 4;
+// 3D launch shapes (opts.tile = index + 1): the 4 x 4 x 4 tile kernel (the
+// default), then columns of tx x ty cells marching through segments of sz
+// planes.  The column kernels compute each face once per segment (3.2 faces
+// per cell for 16 x 8 columns against 3.75 for the tiles) but fit fewer
+// wavefronts per CU; on the 192^3 cube they are not faster in FP32, and
+// their results differ from the tile kernel's in the last bit of a few
+// cells (the two kernels contract multiply-adds differently), so they are
+// taken only when asked for.
+struct Tile3S {
+    int col, tx, ty, sz;
+};
+constexpr Tile3S kTiles3[] = {{0, kTX3, kTY3, kTZ3}, {1, 16, 8, 32}, {1, 16, 8, 48},
+                              {1, 16, 8, 64},        {1, 16, 8, 96}, {1, 8, 8, 48}};
+constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
+static_assert(kNumTiles3 <= kNumTiles2, "the autotuner's arrays hold every shape");
+
+int blocks3(const rtlbfs_mesh &m, int tile) {
+    const Tile3S t = kTiles3[tile];  // sz: the cube tile's depth, or the column's segment length
+    return ((m.n[0] + t.tx - 1) / t.tx) * ((m.n[1] + t.ty - 1) / t.ty) * ((m.n[2] + t.sz - 1) / t.sz);
+}
+
+int threads3(int tile) {
+    const Tile3S t = kTiles3[tile];
+    if (!t.col) return tile3_threads<kTX3, kTY3, kTZ3>();
+    return t.tx == 16 ? col3_threads<16, 8>() : col3_threads<8, 8>();
+}
+
 // A dispatch's grid holds at most 2^32 - 1 work-items (blocks x threads).
 constexpr int64_t kMaxWorkItems = 0xFFFFFFFFll;
 
@@ -114,8 +159,9 @@ bool step_launches_fit(const rtlbfs_mesh &m) {
         }
         return true;
     }
-    const int64_t b = (int64_t)((m.n[0] + kTX3 - 1) / kTX3) * ((m.n[1] + kTY3 - 1) / kTY3) * ((m.n[2] + kTZ3 - 1) / kTZ3);
-    return b * tile3_threads<kTX3, kTY3, kTZ3>() <= kMaxWorkItems;
+    for (int t = 0; t < kNumTiles3; ++t)
+        if ((int64_t)blocks3(m, t) * threads3(t) > kMaxWorkItems) return false;
+    return true;
 }
 constexpr int kRedBlocks = 512;                // blocks of the diagnostics kernels
 
@@ -131,7 +177,7 @@ int step_blocks(const rtlbfs_mesh &m, int tile = 0) {
         const Tile2 t = kTiles2[tile];
         return ((m.n[0] + t.tx - 1) / t.tx) * ((m.n[1] + t.ty - 1) / t.ty);
     }
-    return ((m.n[0] + kTX3 - 1) / kTX3) * ((m.n[1] + kTY3 - 1) / kTY3) * ((m.n[2] + kTZ3 - 1) / kTZ3);
+    return blocks3(m, tile);
 }
 
 
@@ -152,7 +198,7 @@ Layout make_layout(const rtlbfs_mesh &m, int precision) {
     l.off_geo = off;
     off += geometry_bytes(m, precision);
     l.nparts = kRedBlocks;
-    for (int t = 0; t < (m.dim == 2 ? kNumTiles2 : 1); ++t) l.nparts = std::max(l.nparts, step_blocks(m, t));
+    for (int t = 0; t < (m.dim == 2 ? kNumTiles2 : kNumTiles3); ++t) l.nparts = std::max(l.nparts, step_blocks(m, t));
     l.off_parts = off;
     off += align256(sizeof(double) * (size_t)l.nparts * 8);
     l.off_red = off;  // residual sums (8), Nusselt (8), integrals (4), M0 (1), mass-fix sums (4)
@@ -312,10 +358,21 @@ hipError_t launch_step(rtlbfs_t h, int tile, int src, bool res, hipStream_t s) {
             default: return launch_step2d<R, DEV, 8, 8, TL, 2>(d, Uin, Uout, P, ci, co, res, s);
         }
     }
-    const int grid = ((d.n[0] + kTX3 - 1) / kTX3) * ((d.n[1] + kTY3 - 1) / kTY3) * ((d.n[2] + kTZ3 - 1) / kTZ3);
-    constexpr int nt = tile3_threads<kTX3, kTY3, kTZ3>();
-    if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
-    else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
+    const int grid = blocks3(h->mesh, tile);
+    const Tile3S t3 = kTiles3[tile];
+    if (!t3.col) {
+        constexpr int nt = tile3_threads<kTX3, kTY3, kTZ3>();
+        if (res) k_step3d<R, DEV, kTX3, kTY3, kTZ3, true, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
+        else k_step3d<R, DEV, kTX3, kTY3, kTZ3, false, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co);
+    } else if (t3.tx == 16) {
+        constexpr int nt = col3_threads<16, 8>();
+        if (res) k_step3d_col<R, DEV, 16, 8, true, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co, t3.sz);
+        else k_step3d_col<R, DEV, 16, 8, false, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co, t3.sz);
+    } else {
+        constexpr int nt = col3_threads<8, 8>();
+        if (res) k_step3d_col<R, DEV, 8, 8, true, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co, t3.sz);
+        else k_step3d_col<R, DEV, 8, 8, false, TL><<<grid, nt, 0, s>>>(d, Uin, Uout, h->parts(), ci, co, t3.sz);
+    }
     return hipGetLastError();
 }
 
@@ -498,7 +555,7 @@ hipError_t enqueue_mass_fix(rtlbfs_t h, hipStream_t s) {
 // and the tiles are timed in interleaved rounds, keeping each tile's best
 // round, so that clock ramps and neighbours on the device bias no tile.
 int autotune_tile(rtlbfs_t h) {
-    if (h->mesh.dim != 2 || h->curv3) return RTLBFS_OK;
+    if (h->curv3 || (h->mesh.dim == 3 && !h->curv)) return RTLBFS_OK;  // 3D: the tile kernel unless opts.tile
     constexpr int kLaunches = 32, kRounds = 4;
     const int nshapes = h->curv ? kNumTilesC : kNumTiles2;
     auto nsub = [&](int t) { return h->curv ? 1 : kTiles2[t].nsub; };
@@ -838,8 +895,8 @@ int rtlbfs_create(const rtlbfs_mesh *mesh, double Ra, double Pr, double Ma, cons
         }
     }
     // Kernel tile: fixed by opts.tile (1-based), or chosen by the autotuner.
-    if (D == 2 && o.tile > 0) {
-        if (o.tile > kNumTiles2) {
+    if (o.tile > 0) {
+        if (o.tile > (D == 2 ? kNumTiles2 : kNumTiles3)) {
             rtlbfs_destroy(h);
             g_create_err = "opts.tile out of range";
             return RTLBFS_EINVAL;
@@ -1036,9 +1093,9 @@ int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
         out->steps_per_launch = kTiles2[h->tile].nsub;
         out->tile_z = 1;
     } else {
-        out->tile_x = kTX3;
-        out->tile_y = kTY3;
-        out->tile_z = kTZ3;
+        out->tile_x = kTiles3[h->tile].tx;  // columns: tile_z is the segment length
+        out->tile_y = kTiles3[h->tile].ty;
+        out->tile_z = kTiles3[h->tile].sz;
         out->steps_per_launch = 1;
     }
     return RTLBFS_OK;

@@ -35,6 +35,54 @@ constexpr int tile3_threads() {
     return (((TX + 1) * TY * TZ + TX * (TY + 1) * TZ + TX * TY * (TZ + 1)) + 63) / 64 * 64;
 }
 
+// Eq. 55 gradient of the five primitives (r, u_x, u_y, u_z, T) along one
+// axis: (phi_hi - phi_lo) / width with the Eq. 56 face values
+// phi_lo = ls phi_P + ln phi_{P-1} and phi_hi = hs phi_P + hn phi_{P+1}; a
+// wall face takes r_S = r_P, u_S = 0 and T_S = Tw (Tlo / Thi: the wall
+// temperature if isothermal, else T_P).  Shared by the 3D step kernels so
+// they produce the same bits.
+template <typename R>
+__device__ __forceinline__ void grad_axis3(const R (&vP)[5], const R (&vlo)[5], const R (&vhi)[5], R ls, R ln, R hs,
+                                           R hn, R iwP, bool wlo, bool whi, R Tlo, R Thi, R (&g)[5]) {
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        const R flo0 = vP[p] * ls + vlo[p] * ln, fhi0 = vP[p] * hs + vhi[p] * hn;
+        const R zlo = p == 0 ? vP[0] : (p == 4 ? Tlo : (R)0);
+        const R zhi = p == 0 ? vP[0] : (p == 4 ? Thi : (R)0);
+        const R flo = wlo ? zlo : flo0, fhi = whi ? zhi : fhi0;
+        g[p] = (fhi - flo) * iwP;
+    }
+}
+
+// Flux divergence, Boussinesq source and forward-Euler update of one cell
+// (Eqs. 57-59, 64): U^{n+1} = U^n + dt/dV [(F_w - F_e) + (F_s - F_n) +
+// (F_b - F_t)] + dt beta_g rho (T - T_ref) along gravity, where F_w ... F_t
+// are the area-weighted fluxes of its west, east, south, north, bottom and
+// top faces.  FP32 with stochastic rounding adds the increment in one
+// rounding keyed by (cell, step, field).  Shared by the 3D step kernels.
+template <typename R, bool DEV>
+__device__ __forceinline__ void update_cell3(const Domain &d, const Phys<R> &ph, const R (&sc)[5], const R (&fw)[5],
+                                             const R (&fe)[5], const R (&fs)[5], const R (&fn)[5], const R (&fb)[5],
+                                             const R (&ft)[5], R dt_dV, R rhoP, R TP, int64_t c, uint32_t step_key,
+                                             R (&Un)[5]) {
+    const R dtR = ph.dt;
+    if (sizeof(R) == 4 && d.sround) {
+        R inc[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) inc[k] = dt_dV * ((fw[k] - fe[k]) + (fs[k] - fn[k]) + (fb[k] - ft[k]));
+        if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Un[k] = sr_add(sc[k], inc[k], sr_hash((uint32_t)c, step_key * 5u + k));
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const R div = (fw[k] - fe[k]) + (fs[k] - fn[k]) + (fb[k] - ft[k]);
+            Un[k] = sc[k] + dt_dV * div;
+        }
+        if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+    }
+}
+
 template <typename R, bool DEV, int TX, int TY, int TZ, bool RES, bool TL>
 __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, int k0, const R *__restrict__ Uin,
                                              R *__restrict__ Uout, double *__restrict__ part, uint32_t step_key) {
@@ -159,20 +207,15 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
                 const bool wlo = !pq[a] && gq[a] == 0, whi = !pq[a] && gq[a] == nq[a] - 1;
                 const R Tlo = d.kind[2 * a] == kIsothermal ? wall_T<R>(d, 2 * a) : vP[4];
                 const R Thi = d.kind[2 * a + 1] == kIsothermal ? wall_T<R>(d, 2 * a + 1) : vP[4];
-                R vlo[NPRIM], vhi[NPRIM];
+                R vlo[NPRIM], vhi[NPRIM], g[NPRIM];
 #pragma unroll
                 for (int p = 0; p < NPRIM; ++p) {
                     vlo[p] = sp[p][pc - step[a]];
                     vhi[p] = sp[p][pc + step[a]];
                 }
+                grad_axis3<R>(vP, vlo, vhi, ls, ln, hs, hn, iwP, wlo, whi, Tlo, Thi, g);
 #pragma unroll
-                for (int p = 0; p < NPRIM; ++p) {
-                    const R flo0 = vP[p] * ls + vlo[p] * ln, fhi0 = vP[p] * hs + vhi[p] * hn;
-                    const R zlo = p == 0 ? vP[0] : (p == 4 ? Tlo : (R)0);
-                    const R zhi = p == 0 ? vP[0] : (p == 4 ? Thi : (R)0);
-                    const R flo = wlo ? zlo : flo0, fhi = whi ? zhi : fhi0;
-                    sg[p][a][tid] = (fhi - flo) * iwP;
-                }
+                for (int p = 0; p < NPRIM; ++p) sg[p][a][tid] = g[p];
             }
         }
     }
@@ -275,26 +318,18 @@ __device__ __forceinline__ void tile_step_3d(const Domain &d, int i0, int j0, in
             const R rP = sp[0][pc];
             const R rhoP = DEV ? (R)1 + rP : rP;
             const R TP = sp[4][pc];
-            R Un[5];
-            if (sizeof(R) == 4 && d.sround) {
-                R inc[5];
+            R Un[5], sc0[5], fw[5], fe[5], fs[5], fn[5], fb[5], ft[5];
 #pragma unroll
-                for (int k = 0; k < 5; ++k)
-                    inc[k] = dt_dV * ((sf[k][o0] - sf[k][o0 + 1]) + (sf[k][o1] - sf[k][o1 + TX]) +
-                                      (sf[k][o2] - sf[k][o2 + TX * TY]));
-                if (d.gaxis >= 0) inc[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
-#pragma unroll
-                for (int k = 0; k < 5; ++k)
-                    Un[k] = sr_add(sc[k][tid], inc[k], sr_hash((uint32_t)c, step_key * 5u + k));
-            } else {
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    const R div = (sf[k][o0] - sf[k][o0 + 1]) + (sf[k][o1] - sf[k][o1 + TX]) +
-                                  (sf[k][o2] - sf[k][o2 + TX * TY]);
-                    Un[k] = sc[k][tid] + dt_dV * div;
-                }
-                if (d.gaxis >= 0) Un[1 + d.gaxis] += dtR * ph.bg * rhoP * (DEV ? TP : TP - (R)kT0);
+            for (int k = 0; k < 5; ++k) {
+                sc0[k] = sc[k][tid];
+                fw[k] = sf[k][o0];
+                fe[k] = sf[k][o0 + 1];
+                fs[k] = sf[k][o1];
+                fn[k] = sf[k][o1 + TX];
+                fb[k] = sf[k][o2];
+                ft[k] = sf[k][o2 + TX * TY];
             }
+            update_cell3<R, DEV>(d, ph, sc0, fw, fe, fs, fn, fb, ft, dt_dV, rhoP, TP, c, step_key, Un);
 #pragma unroll
             for (int k = 0; k < 5; ++k) Uout[k * N + c] = Un[k];
             if (RES) {
