@@ -252,6 +252,31 @@ int rtlbfs_get_stored(rtlbfs_t h, int field, double *host_out, size_t count);
 int rtlbfs_residual_states(int dim, int precision, int64_t cells, int64_t fstride, const void *old_state,
                            const void *new_state, double *dev_out, void *hip_stream);
 
+/* Checkpoint and bitwise resume.  A run continues bit for bit from a
+ * checkpoint when the new handle has the same mesh, boundaries, physics and
+ * options (seed and noise may differ: the initial state is replaced) and
+ * its state is restored with:
+ *   - the stored fields 0..dim+1 (rtlbfs_get_stored, field after field);
+ *   - rtlbfs_checkpoint: the steps advanced so far (they key the FP32
+ *     stochastic rounding), the steps since the last mass-drift correction,
+ *     and the reference mass that correction restores. */
+typedef struct {
+    int64_t steps;     /* steps advanced so far */
+    int64_t since_fix; /* steps since the last FP32 mass-drift correction */
+    double mass0;      /* sum (rho - 1) dV the correction restores (FP32_DEV) */
+} rtlbfs_checkpoint;
+
+/* Fill *out for the current state (synchronising).  EINVAL on NULL. */
+int rtlbfs_get_checkpoint(rtlbfs_t h, rtlbfs_checkpoint *out);
+
+/* Replace the state by a checkpoint: host_stored holds the dim + 2 stored
+ * fields in the handle's storage form, cells values each, field after field
+ * (count >= (dim + 2) * cells), converted to the storage precision (values
+ * read with rtlbfs_get_stored convert back exactly); ck restores the step
+ * counter, the correction phase and the reference mass (synchronising).
+ * EINVAL on NULL, a short buffer, or a negative step count. */
+int rtlbfs_restore(rtlbfs_t h, const double *host_stored, size_t count, const rtlbfs_checkpoint *ck);
+
 /* Handle facts (host only, no synchronisation). */
 int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out);
 

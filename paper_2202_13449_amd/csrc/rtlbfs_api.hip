@@ -1056,6 +1056,47 @@ int rtlbfs_set_state(rtlbfs_t h, const double *rho, const double *u, const doubl
     return RTLBFS_OK;
 }
 
+int rtlbfs_get_checkpoint(rtlbfs_t h, rtlbfs_checkpoint *out) {
+    if (!h || !out) return RTLBFS_EINVAL;
+    double m0 = 0.0;
+    HIP_TRY(h, hipMemcpyAsync(&m0, h->m0(), sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->steps = h->steps;
+    out->since_fix = h->since_fix;
+    out->mass0 = m0;
+    return RTLBFS_OK;
+}
+
+int rtlbfs_restore(rtlbfs_t h, const double *host_stored, size_t count, const rtlbfs_checkpoint *ck) {
+    if (!h || !host_stored || !ck) return RTLBFS_EINVAL;
+    const int64_t N = h->lay.cells;
+    const int nf = h->mesh.dim + 2;
+    if (count < (size_t)nf * (size_t)N) return fail(h, RTLBFS_EINVAL, "count smaller than (dim + 2) * cells");
+    if (ck->steps < 0 || ck->since_fix < 0) return fail(h, RTLBFS_EINVAL, "negative step count");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const size_t field_bytes = (size_t)h->dom.fstride * elem_size(h->opts.precision);
+    std::vector<double> f((size_t)N);
+    std::vector<char> buf;
+    for (int k = 0; k < nf; ++k) {
+        std::memcpy(f.data(), host_stored + (size_t)k * N, sizeof(double) * (size_t)N);
+        if (h->opts.precision == RTLBFS_FP32_DEV) to_storage<float>(f, buf);
+        else to_storage<double>(f, buf);
+        HIP_TRY(h, hipMemcpyAsync((char *)h->U(h->cur) + k * field_bytes, buf.data(), buf.size(),
+                                  hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    // the step counter of the copy the next launch reads (the stochastic-rounding key)
+    const uint32_t key = (uint32_t)(uint64_t)ck->steps;
+    const double m0 = ck->mass0;
+    HIP_TRY(h, hipMemcpyAsync(h->ctr() + h->cur, &key, sizeof(key), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->m0(), &m0, sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->steps = ck->steps;
+    h->since_fix = ck->since_fix;
+    h->res_valid = false;
+    return RTLBFS_OK;
+}
+
 int rtlbfs_get_info(rtlbfs_t h, rtlbfs_info *out) {
     if (!h || !out) return RTLBFS_EINVAL;
     std::memset(out, 0, sizeof(*out));

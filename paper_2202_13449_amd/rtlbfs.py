@@ -99,6 +99,10 @@ class Info(C.Structure):
     ]
 
 
+class Checkpoint(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("since_fix", C.c_int64), ("mass0", C.c_double)]
+
+
 class RtlbfsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (code {code})")
@@ -165,13 +169,16 @@ def load_library() -> C.CDLL:
     lib.rtlbfs_batch_diverged.argtypes = [VP, C.POINTER(C.c_int)]
     lib.rtlbfs_batch_destroy.argtypes = [VP]
     lib.rtlbfs_residual_states.argtypes = [I, I, I64, I64, VP, VP, VP, VP]
+    lib.rtlbfs_get_checkpoint.argtypes = [VP, C.POINTER(Checkpoint)]
+    lib.rtlbfs_restore.argtypes = [VP, PD, SZ, C.POINTER(Checkpoint)]
     for name in ("rtlbfs_opts_init", "rtlbfs_mesh_nodes", "rtlbfs_create", "rtlbfs_step", "rtlbfs_sync",
                  "rtlbfs_residual", "rtlbfs_nusselt", "rtlbfs_integrals", "rtlbfs_get_field", "rtlbfs_get_stored",
                  "rtlbfs_set_state", "rtlbfs_get_info", "rtlbfs_destroy", "rtlbfs_curv_create", "rtlbfs_wall_heat",
                  "rtlbfs_curv_cells", "rtlbfs_curv3_create", "rtlbfs_curv3_cells", "rtlbfs_batch_create",
                  "rtlbfs_batch_step",
                  "rtlbfs_batch_nusselt", "rtlbfs_batch_residual", "rtlbfs_batch_get_field", "rtlbfs_batch_get_info",
-                 "rtlbfs_batch_sync", "rtlbfs_batch_diverged", "rtlbfs_batch_destroy", "rtlbfs_residual_states"):
+                 "rtlbfs_batch_sync", "rtlbfs_batch_diverged", "rtlbfs_batch_destroy", "rtlbfs_residual_states",
+                 "rtlbfs_get_checkpoint", "rtlbfs_restore"):
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -345,6 +352,18 @@ class Solver:
         out = np.zeros(self.cells)
         self._check(self._lib.rtlbfs_get_stored(self._h, f, _pd(out), out.size), "rtlbfs_get_stored")
         return out
+
+    def checkpoint(self) -> tuple[np.ndarray, Checkpoint]:
+        """The stored fields (dim + 2, cells) and the step counters of the
+        current state."""
+        ck = Checkpoint()
+        self._check(self._lib.rtlbfs_get_checkpoint(self._h, C.byref(ck)), "rtlbfs_get_checkpoint")
+        return np.stack([self.stored(f) for f in range(self.dim + 2)]), ck
+
+    def restore(self, stored: np.ndarray, ck: Checkpoint):
+        """Continue from a checkpoint taken with checkpoint()."""
+        buf = np.ascontiguousarray(stored, dtype=np.float64).reshape(-1)
+        self._check(self._lib.rtlbfs_restore(self._h, _pd(buf), buf.size, C.byref(ck)), "rtlbfs_restore")
 
     def set_state(self, rho: np.ndarray, u: np.ndarray, T: np.ndarray):
         rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)

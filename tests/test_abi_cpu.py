@@ -115,6 +115,9 @@ def test_null_arguments():
     assert lib.rtlbfs_destroy(None) == rt.OK
     assert lib.rtlbfs_opts_init(None) == rt.EINVAL
     assert lib.rtlbfs_mesh_nodes(0, 0.0, None, None) == rt.EINVAL
+    ck = rtb.Checkpoint()
+    assert lib.rtlbfs_get_checkpoint(None, C.byref(ck)) == rt.EINVAL
+    assert lib.rtlbfs_restore(None, None, 0, C.byref(ck)) == rt.EINVAL
     assert isinstance(lib.rtlbfs_last_error(None), bytes)  # last failed create on this thread
     mesh = rt.make_mesh(2, (16, 16))
     bc = rt.make_bc((1, 1, 2, 2), (0.5, -0.5, 0, 0), 1)

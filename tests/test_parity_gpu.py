@@ -275,6 +275,35 @@ def test_empty_and_invalid_calls_on_a_live_handle():
     assert max(field_rel(s, o, 2)) <= FP64_TOL
 
 
+@pytest.mark.parametrize("prec", [rt.FP32_DEV, rt.FP64_PLAIN])
+def test_checkpoint_restore_continues_bit_for_bit(prec):
+    """A run stopped after 200 steps (taken in uneven calls), checkpointed
+    (stored fields, step counter, mass-correction phase and reference mass)
+    and restored into a new handle created with another seed and noise,
+    continues exactly as the uninterrupted 350-step run: every stored field
+    and the Eq. 65 residual, FP32 (stochastic rounding keyed by the step
+    counter, mass correction every 100 steps) and FP64, 2D and 3D."""
+    cases = [(2, (48, 40), (1.5, 1.5), DHC2["kind"], DHC2["Tdev"], DHC2["gaxis"]),
+             (3, (12, 10, 9), (1.8, 1.8, 1.8), DHC3["kind"], DHC3["Tdev"], DHC3["gaxis"])]
+    for args in cases:
+        kw = dict(Ra=1e5, precision=prec, residual_every=50, mass_fix_every=100)
+        a = rt.Solver(*args, seed=3, noise_amp=1e-3, **kw)
+        a.step(350)
+        b = rt.Solver(*args, seed=3, noise_amp=1e-3, **kw)
+        b.step(130)
+        b.step(70)
+        stored, ck = b.checkpoint()
+        assert ck.steps == 200
+        b.close()
+        c = rt.Solver(*args, seed=99, noise_amp=5e-3, **kw)
+        c.restore(stored, ck)
+        c.step(150)
+        for f in range(args[0] + 2):
+            assert np.array_equal(a.stored(f), c.stored(f)), (args[1], f)
+        assert a.residual() == c.residual()
+        assert c.checkpoint()[1].steps == 350
+
+
 @pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP32_DEV])
 def test_two_runs_are_bitwise_identical(prec):
     """Determinism: two handles of the same problem, stepped alike, hold the
