@@ -125,8 +125,13 @@ def test_four_cell_wedge_random_state_parity():
 
 
 def test_annulus_wedge_fp32_deviation():
+    """FP32 deviation storage on the single-layer wedge, which runs the fused
+    one-launch kernel by default, against the FP64 oracle.  (A single-cell
+    periodic layer needs a rotation: with rot = 0 its two periodic vertex
+    layers would coincide, which create rejects.)"""
     X, Y, Z = wedge()
     s, o = make_pair(X, Y, Z, rt.FP32_DEV, **wedge_bc(1))
+    assert (s.info.tile_x, s.info.tile_z) == (16, 4)  # the fused kernel's tile
     s.step(300)
     o.step(300)
     rel = rel_errors(s, o)
@@ -152,17 +157,16 @@ def test_graph_replay_equals_eager_launches_3d():
 @pytest.mark.parametrize("precision", [rt.FP64_PLAIN, rt.FP32_DEV])
 def test_fused_layer_kernel_equals_three_kernels(precision):
     """A single-layer wedge (j periodic with one cell, walls along i and k)
-    runs one fused launch per step by default (opts.tile 0, or 2); opts.tile 1
-    forces the three-launch path.  From a random, non-axisymmetric state on a
+    runs one fused launch per step by default; opts.tile 1 forces the
+    three-launch path.  From a random, non-axisymmetric state on a
     21 x 1 x 27 wedge (ragged 16 x 4 tiles in i and k), both give the same
     fields; the fused path also matches the oracle."""
     X, Y, Z = wedge(nr=21, nz=27, dth=0.1)
     bc = wedge_bc(1, 0.1)
     kw = dict(rot=bc["rot"], Tw=bc["Tw"], up=bc["up"], T_ref=0.5, nu=0.06, chi=0.08, beta_g=bc["beta_g"],
               precision=precision, dt=0.5, residual_every=20)
-    runs = {t: rt.Curv3Solver(X, Y, Z, bc["kind"], tile=t, **kw) for t in (0, 1, 2)}
-    assert (runs[0].info.tile_x, runs[0].info.tile_z) == (16, 4)
-    assert (runs[2].info.tile_x, runs[2].info.tile_z) == (16, 4)
+    runs = {t: rt.Curv3Solver(X, Y, Z, bc["kind"], tile=t, **kw) for t in (0, 1)}
+    assert (runs[0].info.tile_x, runs[0].info.tile_z) == (16, 4)  # the default is the fused kernel
     assert runs[1].info.tile_x == 64 and runs[1].info.tile_z == 1
     rho, u, T = inputs.random_state(runs[0].cells, 3, seed=31)
     for s in runs.values():
@@ -170,8 +174,7 @@ def test_fused_layer_kernel_equals_three_kernels(precision):
         s.step(150)
     tol = FP64_TOL if precision == rt.FP64_PLAIN else 2e-6  # FP64: the oracle parity bar
     for f in range(5):
-        a, b, c = runs[0].field(f), runs[1].field(f), runs[2].field(f)
-        assert np.array_equal(a, c), f
+        a, b = runs[0].field(f), runs[1].field(f)
         scale = max(np.abs(b - (1.0 if f == 0 else 0.0)).max(), 1e-3)
         assert np.abs(a - b).max() <= tol * scale, (f, np.abs(a - b).max() / scale)
     if precision == rt.FP64_PLAIN:
