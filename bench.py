@@ -65,6 +65,7 @@ CSRC = os.path.join(ROOT, "paper_2202_13449_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step2d_fp32_cavity256.json")
 TRAFFIC_FILE_BATCH = os.path.join(ROOT, "profiles", "traffic_k_batch_step2d_256cavities.json")
 TRAFFIC_FILE_3D = os.path.join(ROOT, "profiles", "traffic_k_step3d_cube192.json")
+TRAFFIC_FILE_PROXY = os.path.join(ROOT, "profiles", "traffic_k_step2d_fp32_proxy4788.json")
 
 
 def sources_sha256(headers, api_file, kernel) -> str:
@@ -290,13 +291,19 @@ def batch_steady_bench(rt, torch, steps, warmup, total=200_000, chunk=10_000, to
     while done < total:
         b64.step(chunk)
         b32.step(chunk)
-        b32.sync()
+        for b in (b64, b32):
+            try:
+                b.sync()
+            except rt.RtlbfsError as e:  # a diverged member does not stop the others
+                if e.code != rt.EDIVERGED:
+                    raise
         done += chunk
         res = b64.residuals()
         print(f"batch steady: {done} steps, {int((res.max(axis=1) < tol).sum())} of {len(members)} FP64 members "
               f"below {tol:g}, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
     res64 = b64.residuals()
-    steady = [k for k in range(len(members)) if max(res64[k]) < tol]
+    div = b64.diverged() | b32.diverged()
+    steady = [k for k in range(len(members)) if not div[k] and max(res64[k]) < tol]
     rows = []
     for k in steady:
         a, c = b32.nusselt(k), b64.nusselt(k)
@@ -306,6 +313,7 @@ def batch_steady_bench(rt, torch, steps, warmup, total=200_000, chunk=10_000, to
     worst = max((max(r["nu_rel_diff"].values()) for r in rows), default=None)
     return {"workload": "256 batched cavities, FP32 vs FP64 at steady state", "cells": total_cells(members),
             "steps": done, "tol": tol, "steady_members": len(steady), "members": len(members),
+            "diverged_members": [int(k) for k in np.nonzero(div)[0]],
             "max_nu_rel_diff_steady": worst,
             "members_above_1e-4": int(sum(max(r["nu_rel_diff"].values()) > 1e-4 for r in rows)),
             "rows": rows, "seconds": time.perf_counter() - t0}
@@ -384,13 +392,16 @@ def rb_bench(rt, torch, steps, warmup):
             "seconds_sampling": time.perf_counter() - t0, "tile": list(launch_shape(s.info))}
 
 
+TILE = 0  # --tile: opts.tile of the cube192 and proxy2d workloads (0: the library's default)
+
+
 def cube_bench(rt, torch, steps, warmup):
     """192^3 tanh (phi = 1.8) cubic cavity, Ra = 1e6: FP32 deviation and FP64
-    plain throughput."""
-    out = {"workload": "cube192 tanh1.8 Ra=1e6", "cells": 192 ** 3}
+    plain throughput (launch shape --tile)."""
+    out = {"workload": "cube192 tanh1.8 Ra=1e6", "cells": 192 ** 3, "tile": TILE}
     for name, prec, bpc in (("fp32_dev", rt.FP32_DEV, 40), ("fp64_plain", rt.FP64_PLAIN, 80)):
         s = rt.Solver(3, (192, 192, 192), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=1e6,
-                      Pr=0.71, Ma=MA, precision=prec, seed=1, noise_amp=1e-6)
+                      Pr=0.71, Ma=MA, precision=prec, seed=1, noise_amp=1e-6, tile=TILE)
         s.step(warmup)
         ms = timed(torch, s, steps)
         out[name] = {"ms_per_step": ms, "value": 192 ** 3 / (ms * 1e-3),
@@ -398,6 +409,21 @@ def cube_bench(rt, torch, steps, warmup):
         del s
         torch.cuda.empty_cache()
     return out
+
+
+def proxy2d_bench(rt, torch, steps, warmup, n=4788):
+    """One 4788 x 4788 uniform cavity (22.9M cells, the 256-cavity batch's
+    total) at Ra = 1e7 in FP32 deviation storage with the batch's 16 x 8
+    one-step tile (--tile 4): the batch kernel's per-tile arithmetic on a
+    single domain, for HBM counters and as a throughput reference."""
+    s = rt.Solver(2, (n, n), (0.0, 0.0), KIND, TDEV, GAXIS, Ra=1e7, Pr=PR, Ma=MA, precision=rt.FP32_DEV, seed=1,
+                  noise_amp=1e-6, tile=TILE or 4, residual_every=KERNEL_CHUNK, mass_fix_every=-1)
+    s.step(max(warmup, 20))
+    s.sync()
+    ms = timed(torch, s, max(steps, 50))
+    cells = n * n
+    return {"workload": f"cavity {n}x{n} uniform Ra=1e7 FP32, single domain", "cells": cells,
+            "tile": list(launch_shape(s.info)), **rates(cells, ms, 2, "f32")}
 
 
 TABLE5 = {1e3: {"u_max": 0.132, "z": 0.185, "w_max": 0.133, "x": 0.825, "Nu_m": 1.089, "Nu_o": 1.071},
@@ -494,8 +520,11 @@ def cube_solver(rt, n, prec, **kw):
                      Pr=0.71, Ma=MA, precision=prec, seed=1, noise_amp=1e-6, **kw)
 
 
+CUBE_STEADY_BUDGET_S = 450.0  # --budget-s: wall-clock seconds of the 192^3 FP64 run
+
+
 def cube_steady_bench(rt, torch, steps, warmup, n=192, coarse=80, chunk=20_000, tol=1e-8, coarse_tol=1e-6,
-                      budget_s=560.0):
+                      budget_s=None):
     """C5's fixed-Nu-error check: the 192^3 cube at Ra = 1e6 in FP64 plain
     and FP32 deviation at steady state.  To reach it within one run, both
     start from the same state: the 80^3 FP64 steady solution (hot-wall Nu
@@ -507,6 +536,7 @@ def cube_steady_bench(rt, torch, steps, warmup, n=192, coarse=80, chunk=20_000, 
     FP32 runs the same number of steps.  Progress goes to stderr."""
     from scipy.interpolate import RegularGridInterpolator
 
+    budget_s = CUBE_STEADY_BUDGET_S if budget_s is None else budget_s
     t0 = time.perf_counter()
     c = cube_solver(rt, coarse, rt.FP64_PLAIN, residual_every=1000)
     done, prev = 0, None
@@ -514,6 +544,9 @@ def cube_steady_bench(rt, torch, steps, warmup, n=192, coarse=80, chunk=20_000, 
         c.step(chunk)
         done += chunk
         nu = c.nusselt()["hot_avg"]
+        if done % (10 * chunk) == 0:
+            print(f"cube steady: {coarse}^3 FP64 {done} steps, Nu hot {nu:.7f}, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
         if prev is not None and abs(nu - prev) < coarse_tol * nu:
             break
         prev = nu
@@ -1169,6 +1202,15 @@ def batch_leg(rt, torch, steps, warmup):
     t = stored_traffic(TRAFFIC_FILE_BATCH, batch_sources_sha256(), "16x8")
     out["fp32_dev"]["traffic"] = t
     out["fp32_dev"]["traffic_ratio"] = (t / (BYTES_PER_CELL["f32"] * cells)) if t else None
+    # The batch kernel's per-tile arithmetic (16 x 8 one-step tiles) counted on
+    # one 4788^2 domain of the same total size: HBM bytes over algorithmic.
+    try:
+        with open(TRAFFIC_FILE_PROXY) as f:
+            tp = json.load(f)
+        if tp.get("kernel_sources_sha256") == kernel_sources_sha256():
+            out["fp32_dev"]["traffic_ratio_single_domain_proxy"] = tp["bytes_per_launch"] / tp["algorithmic_bytes_per_step"]
+    except (OSError, ValueError, KeyError):
+        pass
     out["speedup_fp32_vs_fp64"] = out["fp64_plain"]["ms_per_step"] / out["fp32_dev"]["ms_per_step"]
     singles = [rt.Solver(2, (m["n"], m["n"]), (m["stretch"], m["stretch"]), CAVITY_KIND, CAVITY_TDEV,
                          CAVITY_GRAVITY, Ra=m["Ra"], Pr=m["Pr"], Ma=MA, precision=rt.FP32_DEV, seed=4,
@@ -1247,7 +1289,7 @@ def main():
                     help="with --batch: skip the 256 single-domain handles (profiling runs)")
     ap.add_argument("--batch", action="store_true",
                     help="time the 256-cavity batch (one launch per step) against 256 sequential single-domain runs")
-    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "cube192_steady", "steady256", "cube80", "hill", "methods",
+    ap.add_argument("--workload", default="cavity256", choices=["cavity256", "rb1024", "cube192", "cube192_steady", "proxy2d", "steady256", "cube80", "hill", "methods",
                                                            "stability", "cylinder", "cylinder_table4", "annulus", "annulus_table7",
                                                            "dhc_highra"],
                     help="cavity256: the benchmark line; rb1024: 1024x512 Rayleigh-Benard, Ra=1e8; cube192: 192^3 "
@@ -1263,12 +1305,15 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB (5 times) to calibrate HBM counters")
     ap.add_argument("--ra", type=float, default=None,
                     help="dhc_highra (1e7 or 1e8) and cube80 (1e3 ... 1e6): run only this Rayleigh number")
-    ap.add_argument("--budget-s", type=float, default=None, help="dhc_highra: wall-clock seconds per case")
+    ap.add_argument("--budget-s", type=float, default=None,
+                    help="dhc_highra: wall-clock seconds per case; cube192_steady: seconds of the 192^3 FP64 run")
+    ap.add_argument("--tile", type=int, default=0, help="cube192 / proxy2d: opts.tile of the solver")
     ap.add_argument("--steady-steps", type=int, default=0,
                     help="with --batch: advance FP64 and FP32 batches this many steps and compare the Nusselt "
                          "numbers of the members that reached steady state")
     args = ap.parse_args()
-    global HIGHRA_CASES, HIGHRA_BUDGET_S, CUBE80_CASES
+    global HIGHRA_CASES, HIGHRA_BUDGET_S, CUBE80_CASES, TILE, CUBE_STEADY_BUDGET_S
+    TILE = args.tile
     if args.ra is not None:
         if args.workload == "cube80":
             if args.ra not in TABLE5:
@@ -1280,6 +1325,7 @@ def main():
             HIGHRA_CASES = (args.ra,)
     if args.budget_s is not None:
         HIGHRA_BUDGET_S = args.budget_s
+        CUBE_STEADY_BUDGET_S = args.budget_s
     if args.gpus != 1:
         print("bench.py measures one GPU: the RTLBFS step of one domain runs on a single MI355X; "
               "multi-GPU sharding is not implemented (use --gpus 1)", file=sys.stderr)
@@ -1308,7 +1354,8 @@ def main():
               flush=True)
         return
     if args.workload != "cavity256":
-        fn = {"rb1024": rb_bench, "cube192": cube_bench, "cube192_steady": cube_steady_bench, "steady256": steady_bench,
+        fn = {"rb1024": rb_bench, "cube192": cube_bench, "cube192_steady": cube_steady_bench, "proxy2d": proxy2d_bench,
+              "steady256": steady_bench,
               "cube80": cube_table5_bench, "hill": hill_bench, "methods": methods_bench,
               "stability": stability_bench, "cylinder": cylinder_bench,
               "cylinder_table4": cylinder_table4_bench, "annulus": annulus_bench,
