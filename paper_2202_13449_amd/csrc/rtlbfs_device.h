@@ -135,8 +135,12 @@ struct Side {
     R g[D][D + 2];
 };
 
-// Interior-face flux per unit area along +n (Sec. 3.2) for D = 2 (D2Q9 node
-// offsets) or D = 3 (D3Q19 offsets).  DEV selects the deviation storage
+// Interior-face flux per unit area along +n (Sec. 3.2), nodal form, for D = 2
+// (D2Q9 node offsets) or D = 3 (D3Q19 offsets).  The kernels use face_flux
+// below, which evaluates the same differences from the column polynomials;
+// this form follows the paper node by node and fixes the algorithmic
+// operation count (it is instantiated by the host-side operation counter and
+// the host check that the two forms agree).  DEV selects the deviation storage
 // (r = rho - 1, theta = rho (T - T0)); otherwise r is rho and T absolute.
 // fdir: buoyancy unit vector in the local frame (added as dt * F at the face
 // centre to the predicted momentum).  out = {mass, m_0..m_{D-1}, energy}.
@@ -148,7 +152,7 @@ struct Side {
 // D_k f = (f(+k) - f(-k))/2h, D_kk f = (f(+k) - 2 f(0) + f(-k))/h^2,
 // D_kl f = (f(+k+l) - f(+k-l) - f(-k+l) + f(-k-l))/4h^2.
 template <typename R, int D, bool DEV, bool TB = false>
-__host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR, const R (&fdir)[D],
+__host__ __device__ inline void face_flux_nodes(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR, const R (&fdir)[D],
                                  const Phys<R> &ph, R (&out)[D + 2]) {
     constexpr int NP = D + 2;
     const R cs2 = (R)kCs2;
@@ -270,6 +274,165 @@ __host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> 
     if (DEV) {
         // theta = e - T0 rho is advanced with Q - T0 P; e* = T0 rho_e* + theta*
         // with rho_e* - rho* = -dt^2/2 d_a d_b (rho u_a u_b).
+        fe += (R)kT0 * (-(ph.tau_g - half) * dm[0] - ph.chi * Dr[0] + (ph.tau_g - (R)1.5) * ms[0] * dt2h * ddK * inv_rhos);
+    }
+    out[D + 1] = fe;
+}
+
+// Interior-face flux per unit area along +n (Sec. 3.2), column form: the
+// same predictor (Eqs. 46-48) and fluxes (Eqs. 57-59) as face_flux_nodes,
+// with the central differences taken from polynomial coefficients instead of
+// node values.  The node X = x_S + h (a n + b t1 + c t2) lies in column a;
+// along the tangents every primitive of a column is affine (Eq. 29), so a
+// product of two primitives is quadratic in (b, c) and of three cubic.  A
+// tangential first difference over nodes +-1 is the polynomial's odd part, a
+// second difference its quadratic coefficient (zero for a single primitive),
+// and a mixed difference over four corner nodes its b c coefficient (taken
+// in the columns a = +-1 for the normal-tangent pairs).  Exact in exact
+// arithmetic, with fewer operations than the nodal form and no rounding
+// noise in differences that vanish exactly.  Arguments as for
+// face_flux_nodes.
+template <typename R, int D, bool DEV, bool TB = false>
+__host__ __device__ inline void face_flux(const Side<R, D> &L, const Side<R, D> &Rt, R dL, R dR, const R (&fdir)[D],
+                                 const Phys<R> &ph, R (&out)[D + 2]) {
+    constexpr int NP = D + 2;
+    const R cs2 = (R)kCs2;
+    const R half = (R)0.5;
+    // Column a (0: a = -1, from the left cell; 2: a = +1, from the right
+    // cell; 1: a = 0, the mean of both): the primitives on the column's
+    // centre line B[a][p] and their slopes per lattice step along each
+    // tangent S[a][k][p] (Eq. 29).
+    R B[3][NP], S[3][D][NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        B[0][p] = L.v[p] + L.g[0][p] * (dL - ph.h);
+        B[2][p] = Rt.v[p] + Rt.g[0][p] * (ph.h - dR);
+        B[1][p] = half * ((L.v[p] + L.g[0][p] * dL) + (Rt.v[p] - Rt.g[0][p] * dR));
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            S[0][k][p] = ph.h * L.g[k][p];
+            S[2][k][p] = ph.h * Rt.g[k][p];
+            S[1][k][p] = half * (S[0][k][p] + S[2][k][p]);
+        }
+    }
+    const R w1 = ph.inv2h, w2 = ph.invh2, w4 = ph.inv4h2;
+    const R w1x2 = w1 + w1, w2x2 = w2 + w2;
+    // Centre-line conserved values of each column.
+    R rho[3], m[3][D], e[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rho[a] = DEV ? (R)1 + B[a][0] : B[a][0];
+#pragma unroll
+        for (int q = 0; q < D; ++q) m[a][q] = rho[a] * B[a][1 + q];
+        e[a] = rho[a] * B[a][D + 1];
+    }
+    // Normal direction: nodes (+-1, 0, 0) and the centre.
+    R Dn_m[D], lapm[D], divK[D], gdm[D], Da_mn[D], Dr[D];
+    R mn_un[3], e_un[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        mn_un[a] = m[a][0] * B[a][1];
+        e_un[a] = e[a] * B[a][1];
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        Dn_m[q] = w1 * (m[2][q] - m[0][q]);
+        lapm[q] = w2 * ((m[2][q] - m[1][q]) + (m[0][q] - m[1][q]));
+        divK[q] = w1 * (m[2][q] * B[2][1] - m[0][q] * B[0][1]);
+    }
+    const R Dne = w1 * (e[2] - e[0]);
+    R lape = w2 * ((e[2] - e[1]) + (e[0] - e[1]));
+    Dr[0] = w1 * (B[2][0] - B[0][0]);
+    const R lapr = w2 * ((B[2][0] - B[1][0]) + (B[0][0] - B[1][0]));
+    R divq = w1 * (e_un[2] - e_un[0]);
+    R ddK = w2 * ((mn_un[2] - mn_un[1]) + (mn_un[0] - mn_un[1]));
+    Da_mn[0] = Dn_m[0];
+    R divm = Dn_m[0];
+    gdm[0] = lapm[0];
+    // Tangent k: in column a = 0 every field is affine along the tangent, so
+    // products of two fields are quadratic and of three cubic; the central
+    // differences of Eqs. 46-48 are their odd and even coefficients.  The
+    // mixed differences with the normal take the odd coefficients of the
+    // columns a = +-1.
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+        const R sr = S[1][k][0], sT = S[1][k][D + 1];
+        const R uk = B[1][1 + k], sk = S[1][k][1 + k];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const R uq = B[1][1 + q], sq = S[1][k][1 + q];
+            lapm[q] += w2x2 * (sr * sq);
+            divK[q] += w1x2 * (sr * (uq * uk + sq * sk) + rho[1] * (sq * uk + uq * sk));
+        }
+        const R Dk_mk = w1x2 * (rho[1] * sk + sr * uk);
+        Da_mn[k] = w1x2 * (rho[1] * S[1][k][1] + sr * B[1][1]);
+        divm += Dk_mk;
+        Dr[k] = w1x2 * sr;
+        lape += w2x2 * (sr * sT);
+        divq += w1x2 * (sr * (B[1][D + 1] * uk + sT * sk) + rho[1] * (sT * uk + B[1][D + 1] * sk));
+        ddK += w2x2 * (sk * (rho[1] * sk + (R)2 * sr * uk));
+        gdm[k] = w2x2 * (sr * sk);
+        // (n, k) corners: nodes (+-1, +-1 along k).
+        R om_k[2], om_n[2], omu[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int a = 2 * j;
+            const R ar = S[a][k][0], an = S[a][k][1], ak = S[a][k][1 + k];
+            const R Un = B[a][1], Uk = B[a][1 + k];
+            om_k[j] = rho[a] * ak + ar * Uk;
+            om_n[j] = rho[a] * an + ar * Un;
+            omu[j] = ar * (Un * Uk + an * ak) + rho[a] * (an * Uk + Un * ak);
+        }
+        const R w4x2 = w4 + w4;
+        gdm[0] += w4x2 * (om_k[1] - om_k[0]);
+        gdm[k] += w4x2 * (om_n[1] - om_n[0]);
+        ddK += (R)2 * w4x2 * (omu[1] - omu[0]);
+    }
+    if constexpr (D == 3) {
+        // (t1, t2) corners: nodes (0, +-1, +-1); the sum of b c f over the four
+        // is 4 times the b c coefficient of f.
+        const R r1 = S[1][1][0], r2 = S[1][2][0];
+        const R U1 = B[1][2], U2 = B[1][3];
+        const R a1 = S[1][1][2], a2 = S[1][2][2];  // slopes of u_1 along t1, t2
+        const R c1 = S[1][1][3], c2 = S[1][2][3];  // slopes of u_2 along t1, t2
+        const R bc_m1 = r1 * a2 + r2 * a1;
+        const R bc_m2 = r1 * c2 + r2 * c1;
+        const R bc_m1u2 = r1 * (a2 * U2 + U1 * c2) + r2 * (a1 * U2 + U1 * c1) + rho[1] * (a1 * c2 + a2 * c1);
+        const R w4x4 = (R)4 * w4;
+        gdm[1] += w4x4 * bc_m2;
+        gdm[2] += w4x4 * bc_m1;
+        ddK += (R)2 * w4x4 * bc_m1u2;
+    }
+    const R r0 = B[1][0], e0 = e[1], T0n = B[1][D + 1];
+    R m0[D], K0n[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        m0[q] = m[1][q];
+        K0n[q] = m[1][q] * B[1][1];
+    }
+    const R q0n = e[1] * B[1][1];
+    const R dt = ph.dtl, dt2h = half * ph.dtl * ph.dtl;
+    const R rho0 = rho[1];
+    const R Fb = ph.bg * rho0 * (TB ? T0n - ph.Tref_s : (DEV ? T0n : T0n - (R)kT0));
+    const R dr = -dt * divm + dt2h * (ddK + cs2 * lapr);
+    R dm[D], ms[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        dm[q] = -dt * (divK[q] + cs2 * Dr[q]) + cs2 * dt2h * (lapm[q] + (R)2 * gdm[q]) + dt * fdir[q] * Fb;
+        ms[q] = m0[q] + dm[q];
+    }
+    const R de = -dt * divq + cs2 * dt2h * lape;
+    const R rhos = rho0 + dr, es = e0 + de;
+    const R inv_rhos = recip(rhos);
+    out[0] = ms[0];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        R f = K0n[q] - ph.nu * (Dn_m[q] + Da_mn[q]) - (ph.tau_f - (R)1.5) * (ms[q] * ms[0] * inv_rhos - K0n[q]);
+        if (q == 0) f += cs2 * r0 - ph.nu * divm - (ph.tau_f - (R)1.5) * cs2 * dr;
+        out[1 + q] = f;
+    }
+    R fe = q0n - ph.chi * Dne - (ph.tau_g - (R)1.5) * (ms[0] * es * inv_rhos - q0n);
+    if (DEV) {
         fe += (R)kT0 * (-(ph.tau_g - half) * dm[0] - ph.chi * Dr[0] + (ph.tau_g - (R)1.5) * ms[0] * dt2h * ddK * inv_rhos);
     }
     out[D + 1] = fe;
