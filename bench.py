@@ -907,14 +907,16 @@ def dhc_highra_bench(rt, torch, steps, warmup, tol=1e-8, chunk=100_000, plateau=
 
 
 # Body-fitted meshes (Sec. 4.3).  Flops per cell-update of the curvilinear
-# step kernel: two faces (545 FP32-deviation / 523 FP64-plain each, the
-# library's frame functions counted by tests/test_flops_cpu.py) + Eq. 55
-# Gauss gradients over four faces 152 (4 x (4 Eq. 56 values x 4 + normals 4
-# + 4 x 2 x 2 accumulations) + 8 area scalings) + primitives 5 (4) + update
-# and buoyancy 32 (31) + stochastic rounding 24.  Bytes per cell: state read
-# and written (32 / 64) + two face records of 8 values (64 / 128) + 1/dV
-# (4 / 8).
+# step kernel in the nodal form: two faces (545 FP32-deviation / 523
+# FP64-plain each: the frame rotation, shift and flux the kernels run, 430 /
+# 415 by tests/test_flops_cpu.py, plus the 115 / 108 by which the nodal face
+# flux exceeds the column form) + Eq. 55 Gauss gradients over four faces 152
+# (4 x (4 Eq. 56 values x 4 + normals 4 + 4 x 2 x 2 accumulations) + 8 area
+# scalings) + primitives 5 (4) + update and buoyancy 32 (31) + stochastic
+# rounding 24.  Bytes per cell: state read and written (32 / 64) + two face
+# records of 8 values (64 / 128) + 1/dV (4 / 8).
 FLOPS_PER_CELL_CURV = {"f32": 2 * 545 + 152 + 5 + 32 + 24, "f64": 2 * 523 + 152 + 4 + 31}
+EXEC_FLOPS_PER_CELL_CURV = {"f32": 2 * 430 + 152 + 5 + 32 + 24, "f64": 2 * 415 + 152 + 4 + 31}
 BYTES_PER_CELL_CURV = {"f32": 32 + 64 + 4, "f64": 64 + 128 + 8}
 TABLE4 = {0.0: (2.438, 43.65), 100.0: (2.653, 29.91), 800.0: (3.202, 0.0), 1600.0: (3.508, 0.0)}
 
@@ -980,6 +982,7 @@ def cylinder_bench(rt, torch, steps, warmup):
         out[name] = {"ms_per_step": ms, "value": cells / (ms * 1e-3), "kernel_us": ms * 1e3, "tflops": tf,
                      "tile": [s.info.tile_x, s.info.tile_y],
                      "frac": tf / peak, "peak": peak, "flops_per_cell": FLOPS_PER_CELL_CURV[key],
+                     "executed_flops_per_cell": EXEC_FLOPS_PER_CELL_CURV[key],
                      "bytes_per_cell": BYTES_PER_CELL_CURV[key],
                      "hbm_gbs": BYTES_PER_CELL_CURV[key] * cells / (ms * 1e-3) / 1e9}
         if key == "f32":
