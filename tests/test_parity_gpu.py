@@ -405,6 +405,57 @@ def test_c2_full_size_fp32_in_the_benchmarked_configuration(tile):
     assert max(own) <= 1e-5, own  # measured: about 4e-7
 
 
+def step_from_gpu_state(s, o, dim, nsteps):
+    """Hand the GPU's stored fields to the oracle (FP32 values are exact in
+    FP64; both sides store r = rho - 1 or rho, m, theta = rho (T - T0) or
+    the plain energy alike), then advance both by nsteps."""
+    for f in range(dim + 2):
+        o.set_stored(f, s.stored(f))
+    s.step(nsteps)
+    o.step(nsteps)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP32_DEV])
+def test_c3_full_size_steps_from_a_developed_state(prec):
+    """The 1024 x 512 periodic Rayleigh-Benard box at Ra = 1e8 as the
+    benchmark runs it (conduction profile plus 1e-3 noise, seed 3, the
+    autotuned launch shape, graph-replayed chunks): after 20,000 GPU steps
+    the state is handed to the oracle and both advance 4 steps.  Every cell
+    of every field is compared on P14's scale, max |oracle|, which needs a
+    developed flow: a few hundred steps from rest the velocity is still at
+    the level of the rounding of the hydrostatic balance.  1e-12 in FP64; in
+    FP32 the GPU's own rounding of 4 steps, held to 1e-6."""
+    s, o = make_pair(2, (1024, 512), (0.0, 0.0), (0, 0, 1, 1), (0.0, 0.0, 0.5, -0.5), 1, Ra=1e8, noise=1e-3,
+                     seed=3, init=INIT_CONDUCTION, precision=prec)
+    print("C3 full size, tile", (s.info.tile_x, s.info.tile_y, s.info.steps_per_launch), flush=True)
+    s.step(20000)
+    step_from_gpu_state(s, o, 2, 4)
+    rel = field_rel(s, o, 2, Vc=0.0)
+    print("C3 4 steps from step 20000:", rel, "max |u|", float(np.abs(o.prim(1)).max()), flush=True)
+    assert max(rel) <= (FP64_TOL if prec == rt.FP64_PLAIN else 1e-6), rel
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP32_DEV])
+def test_c5_full_size_step_from_a_developed_state(prec):
+    """The 192^3 tanh (phi = 1.8) cube at Ra = 1e6 as the benchmark runs it
+    (the default 4 x 4 x 4 tiles, graph-replayed chunks): after 3,000 GPU
+    steps (the wall layers developed; P14's scale max |oracle| needs them)
+    the state is handed to the oracle and both advance one step.  All
+    7,077,888 cells of every field are compared on that scale: 1e-12 in
+    FP64, 1e-6 in FP32."""
+    s, o = make_pair(3, (192, 192, 192), (1.8, 1.8, 1.8), (1, 1, 2, 2, 2, 2), (-0.5, 0.5, 0, 0, 0, 0), 2, Ra=1e6,
+                     noise=1e-6, precision=prec)
+    print("C5 full size, tile", (s.info.tile_x, s.info.tile_y, s.info.tile_z), flush=True)
+    s.step(3000)
+    step_from_gpu_state(s, o, 3, 1)
+    rel = field_rel(s, o, 3, Vc=0.0)
+    print("C5 1 step from step 3000:", rel, "max |u|", float(np.abs(o.prim(1)).max()), flush=True)
+    assert max(rel) <= (FP64_TOL if prec == rt.FP64_PLAIN else 1e-6), rel
+    o.close()
+
+
 @pytest.mark.parametrize("prec", [rt.FP64_PLAIN, rt.FP64_DEV])
 def test_buoyancy_in_the_update_only_parity(prec):
     """The paper-literal placement of Eq. 64 (force in the cell update only,
