@@ -9,6 +9,33 @@
 
 namespace rtlbfs {
 
+// Thread t of the block adds rows b0 + t, b0 + t + blockDim.x, ... (below
+// b1) of K doubles into acc, in that order.  The loads of eight rows are
+// issued before their additions, so a long range is not bound by one load
+// latency per row; the order of the additions is the same as one row at a
+// time.
+template <int K>
+__device__ inline void strided_row_sums(const double *__restrict__ parts, int64_t b0, int64_t b1,
+                                        double (&acc)[K]) {
+    constexpr int U = 8;
+    const int64_t stride = blockDim.x;
+    int64_t b = b0 + threadIdx.x;
+    for (; b + (U - 1) * stride < b1; b += U * stride) {
+        double v[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[u][k] = parts[(b + u * stride) * K + k];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += v[u][k];
+    }
+    for (; b < b1; b += stride)
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += parts[b * K + k];
+}
+
 // Sum `nparts` rows of K doubles into out[0..K): one block, fixed order.
 template <int K>
 __global__ void __launch_bounds__(256) k_finalize_sum(const double *__restrict__ parts, int nparts,
@@ -17,9 +44,7 @@ __global__ void __launch_bounds__(256) k_finalize_sum(const double *__restrict__
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += parts[(int64_t)b * K + k];
+    strided_row_sums<K>(parts, 0, nparts, acc);
     block_sums<K>(acc, sred);
     if (threadIdx.x == 0)
 #pragma unroll
@@ -201,9 +226,7 @@ __global__ void __launch_bounds__(256) k_segment_sum(const double *__restrict__ 
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int b = begin[m] + threadIdx.x; b < begin[m + 1]; b += blockDim.x)
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += parts[(int64_t)b * K + k];
+    strided_row_sums<K>(parts, begin[m], begin[m + 1], acc);
     block_sums<K>(acc, sred);
     if (threadIdx.x == 0)
 #pragma unroll
