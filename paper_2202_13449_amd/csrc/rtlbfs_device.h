@@ -77,7 +77,9 @@ __device__ inline double wave_max(double v) {
 }
 
 // Block-wide sums of K values; the result is valid in thread 0.  `scratch`
-// holds K * (blockDim/64) doubles of shared memory.
+// holds K * (blockDim/64) doubles of shared memory.  Thread k < K adds the
+// wave sums of value k in wave order (the same order for every launch
+// shape), so the K chains run side by side.
 template <int K>
 __device__ inline void block_sums(double (&v)[K], double *scratch) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -86,12 +88,16 @@ __device__ inline void block_sums(double (&v)[K], double *scratch) {
     if (lane == 0)
         for (int k = 0; k < K; ++k) scratch[k * nw + wave] = v[k];
     __syncthreads();
+    if (threadIdx.x < K) {
+        const int k = threadIdx.x;
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += scratch[k * nw + w];
+        scratch[k * nw] = s;  // only this thread reads row k
+    }
+    __syncthreads();
     if (threadIdx.x == 0)
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += scratch[k * nw + w];
-            v[k] = s;
-        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = scratch[k * nw];
     __syncthreads();
 }
 
